@@ -1,0 +1,116 @@
+"""CPU oracle of the X-engine correlation -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
+leg may import this package.  It shares no code with the HIP path.
+
+``correlate`` returns the plain definition of the X-engine output (Sec. I;
+Sec. IV-C, "Full Correlation"; Eq. (1) counts the N(N+1)/2 baselines):
+``V_f[i][j] = sum_t x_i conj(x_j)`` over the upper triangle including the
+diagonal, as int64 ``[F][N(N+1)/2][2]`` (re, im), computed by the C loop nest in
+``xeng_oracle.c``.
+
+Parity pins (see ``tests/test_oracle_pins.py``): a hand-worked example, closed
+forms for constant, single-tone and two-tone inputs, Gram-matrix invariants,
+numpy complex128 ``X @ X^H``, pure-Python brute force, the exhaustive 256 x 256
+code pairs and the int32 boundary.  The gated variant is pinned by summing its
+gates back to the ungated result and by brute force.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import build as _build
+
+_LIBS: dict = {}
+
+
+def load(mutant: Optional[str] = None, path: Optional[str] = None) -> ctypes.CDLL:
+    """Load (building it first if absent) the oracle library."""
+    key = path or mutant or ""
+    if key in _LIBS:
+        return _LIBS[key]
+    p = path or _build.lib_path(mutant)
+    if not os.path.exists(p):
+        p = _build.build(mutant)
+    lib = ctypes.CDLL(p)
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.oracle_correlate_range.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, i64p,
+                                           ctypes.c_int]
+    lib.oracle_correlate_range.restype = ctypes.c_int
+    lib.oracle_correlate_gated.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip,
+                                           ctypes.c_int, i64p]
+    lib.oracle_correlate_gated.restype = ctypes.c_int
+    lib.oracle_threads.restype = ctypes.c_int
+    _LIBS[key] = lib
+    return lib
+
+
+def threads(lib: Optional[ctypes.CDLL] = None) -> int:
+    return int((lib or load()).oracle_threads())
+
+
+def correlate(samples: np.ndarray, channels: Optional[Sequence[int]] = None,
+              t0: int = 0, t1: Optional[int] = None, full: bool = False,
+              lib: Optional[ctypes.CDLL] = None) -> np.ndarray:
+    """Visibilities of ``samples[T][F][N]`` (uint8).
+
+    Returns int64 ``[F_sel][N(N+1)/2][2]``, or ``[F_sel][N][N][2]`` (the whole
+    Hermitian matrix) with ``full=True``; ``channels`` selects channels and
+    ``[t0, t1)`` the integrated time range.
+    """
+    s = np.ascontiguousarray(samples, dtype=np.uint8)
+    if s.ndim != 3:
+        raise ValueError("samples must be [T][F][N]")
+    T, F, N = s.shape
+    t1 = T if t1 is None else int(t1)
+    chans = list(range(F)) if channels is None else [int(c) for c in channels]
+    nb = N * (N + 1) // 2
+    shape = (len(chans), N, N, 2) if full else (len(chans), nb, 2)
+    out = np.zeros(shape, dtype=np.int64)
+    ch = (ctypes.c_int * max(1, len(chans)))(*chans)
+    lib = lib or load()
+    rc = lib.oracle_correlate_range(
+        s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), N, F, T, ch, len(chans), int(t0), t1,
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 1 if full else 0)
+    if rc != 0:
+        raise ValueError(f"oracle_correlate_range failed ({rc})")
+    return out
+
+
+def correlate_gated(samples: np.ndarray, gate: np.ndarray, G: int,
+                    lib: Optional[ctypes.CDLL] = None) -> np.ndarray:
+    """Gated visibilities int64 ``[G][F][N(N+1)/2][2]``; ``gate[t]`` picks the buffer."""
+    s = np.ascontiguousarray(samples, dtype=np.uint8)
+    T, F, N = s.shape
+    g = np.ascontiguousarray(gate, dtype=np.int32)
+    if g.shape != (T,):
+        raise ValueError("gate must have one entry per time sample")
+    nb = N * (N + 1) // 2
+    out = np.zeros((G, F, nb, 2), dtype=np.int64)
+    lib = lib or load()
+    rc = lib.oracle_correlate_gated(
+        s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), N, F, T,
+        g.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), int(G),
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise ValueError(f"oracle_correlate_gated failed ({rc})")
+    return out
+
+
+def tri_index(i: int, j: int, N: int) -> int:
+    """Row-major upper-triangle position of baseline (i, j), i <= j."""
+    return i * N - i * (i - 1) // 2 + (j - i)
+
+
+def to_int32(v: np.ndarray) -> np.ndarray:
+    """Narrow oracle sums to the int32 output type, refusing any that do not fit."""
+    if v.size and (v.min() < np.iinfo(np.int32).min or v.max() > np.iinfo(np.int32).max):
+        raise OverflowError("visibility outside int32")
+    return v.astype(np.int32)
