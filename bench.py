@@ -1,0 +1,158 @@
+#!/usr/bin/env python3
+"""Benchmark of the X-engine on one MI355X.
+
+One step = one call of the correlation over a whole frame of the full-array
+workload (N = 2048 inputs, F = 16 channels, T = 32768 samples, seeded
+correlated-Gaussian 4+4-bit data with 5% toned channels), inputs resident in
+HBM.  Prints one JSON line: useful complex MACs per second (F T N(N+1)/2 per
+frame, Eq. (1)), the fraction of the int8 MFMA peak (8 ops per complex MAC),
+channels sustained in real time at the 2.56 us sample period (2^23 samples in
+21.47 s), and the kernel's roofline figures, next to the CPU oracle timed on a
+bounded sample of the same frame.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("complex MACs/s and % int8 MFMA peak at N=2048; channels sustained real-time; "
+          "p99 frame latency")
+PEAK_TOPS = {"i8": 5000.0, "f8": 5000.0}   # dense MFMA peaks of MI355X (int8 TOP/s, FP8 TFLOP/s)
+SAMPLE_PERIOD_S = 21.47 / 2 ** 23          # one sample per channel every 2.56 us
+CHANNEL_MHZ = 400.0 / 1024                 # 1024 channels over 400 MHz
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="full_array",
+                    help="full_array (default), pathfinder, precision or tiny")
+    ap.add_argument("--form", default="i8", choices=["i8", "f8"])
+    ap.add_argument("--split-t", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="measured HBM bytes per launch (from rocprofv3 counters), if present")
+    return ap.parse_args()
+
+
+def cpu_baseline(frame, w):
+    """The oracle on channel 0 of the same frame, all T samples (1/F of the work)."""
+    import oracle
+
+    lib = oracle.load()
+    t0 = time.perf_counter()
+    oracle.correlate(frame, channels=[0], lib=lib)
+    dt = time.perf_counter() - t0
+    cmac = w.T * w.baselines
+    return {"value": cmac / dt, "unit": "cMAC/s", "cores": oracle.threads(lib), "kind": "oracle",
+            "sample": f"channel 0 of the {w.name} frame, all {w.T} samples "
+                      f"({cmac:.3e} complex MACs, {dt:.1f} s)",
+            "cpu": platform.processor() or platform.machine()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this X-engine benchmark runs on exactly one GPU; the correlation of "
+              "each channel is independent, and multi-GPU runs are not part of this build "
+              "(see the sharding paragraph of the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1503_06202_amd import Plan, vis_shape
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = synth.workload(args.workload)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    frame = synth.gen_frame(w.N, w.F, w.T, w.seed, w.kind)
+    gen_s = time.perf_counter() - t0
+    d = torch.from_numpy(frame).to(dev)
+    vis = torch.empty(vis_shape(w.N, w.F), dtype=torch.int32, device=dev)
+    plan = Plan(w.N, w.F, w.T, form=args.form, split_t=args.split_t)
+    stream = torch.cuda.current_stream()
+    print(f"bench: workload {w.name} N={w.N} F={w.F} T={w.T} form={args.form} "
+          f"(generated in {gen_s:.1f} s)", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        plan.correlate(d, vis, stream)
+    torch.cuda.synchronize()
+
+    # per-launch timing with events on the stream the kernels are launched on
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        plan.correlate(d, vis, stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ev_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    ms_step = wall * 1e3 / args.steps
+    ev_avg = sum(ev_ms) / len(ev_ms)
+
+    cmac = w.cmac
+    value = cmac / (ms_step / 1e3)
+    ops_per_launch = 8.0 * cmac          # 1 complex MAC = 4 real MACs = 8 ops
+    achieved = ops_per_launch / (ev_avg / 1e3) / 1e12
+    peak = PEAK_TOPS[args.form]
+    frame_s = w.T * SAMPLE_PERIOD_S
+    channels_rt = w.F * frame_s / (ms_step / 1e3)
+
+    traffic = None
+    if os.path.exists(args.traffic):
+        with open(args.traffic) as fh:
+            tr = json.load(fh)
+        key = f"{w.name}/{args.form}"
+        if key in tr:
+            traffic = tr[key].get("bytes_per_launch")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cMAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int8" if args.form == "i8" else "fp8-e4m3",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": w.N, "F": w.F, "T": w.T, "recipe": w.kind,
+                   "seed": w.seed, "form": args.form, "baselines_per_channel": w.baselines,
+                   "parallelism": "single GPU (channels independent)"},
+        "pct_mfma_peak": 100.0 * achieved / peak,
+        "realtime_channels": channels_rt,
+        "mhz_per_gpu": channels_rt * CHANNEL_MHZ,
+        "kernel_ms_avg": ev_avg,
+        "kernel_ms_min": min(ev_ms),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(frame, w)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * xeng.h -- C ABI of the MI355X (gfx950) correlator X-engine.
+ *
+ * The engine computes, for every frequency channel f of a frame of 4+4-bit
+ * complex samples, the integrated pairwise products of all inputs (Sec. I;
+ * Sec. IV-C, "Full Correlation"):
+ *
+ *     V_f[i][j] = sum_{t < T} x[t][f][i] * conj(x[t][f][j]),   0 <= i <= j < N,
+ *
+ * the N(N+1)/2 baselines of Eq. (1), autocorrelations included.  All sums are
+ * exact integers.
+ *
+ * Data layout (shared by every entry point):
+ *   samples  device memory, uint8 [T][F][N] (N fastest).  One byte per complex
+ *            sample: high nibble = real part + 8, low nibble = imaginary part
+ *            + 8 (offset binary, Sec. II-A footnote).  Every byte is a valid
+ *            sample; there is no reserved code.
+ *   vis      device memory, int32 [F][N(N+1)/2][2]: for each channel the upper
+ *            triangle in row-major order, baseline (i, j) at
+ *            b(i, j) = i*N - i*(i-1)/2 + (j - i), stored as (re, im).
+ *            Im of every autocorrelation (i == j) is 0.
+ *
+ * Ownership: samples and vis belong to the caller; the library neither frees
+ * them nor keeps them past the call.  A plan owns its own workspace.
+ *
+ * Execution: every compute entry point is asynchronous and ordered on the
+ * caller's HIP stream (a hipStream_t passed as void*; NULL is the null
+ * stream).  No host synchronisation and no host allocation happen on the call
+ * path of xeng_correlate.  A plan is not re-entrant: at most one call in flight
+ * per plan; distinct plans are independent.
+ *
+ * Errors: functions return XENG_OK (0) or a negative code; nothing throws
+ * across the ABI.  XENG_EINVAL, XENG_EPLAN and XENG_EOVERFLOW are decided on
+ * the host before any HIP call, so they are reported even without a GPU.
+ * XENG_EHIP carries a HIP runtime or launch error; its text is kept per plan
+ * (xeng_plan_error).
+ *
+ * Exactness: int32 holds every result while T <= 2^24 - 1 (|Re| <= 128 T).
+ * Calls with a larger T fail with XENG_EOVERFLOW; integrate longer by calling
+ * again with XENG_ACCUMULATE and dumping before int32 would overflow.
+ */
+#ifndef XENG_H
+#define XENG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct xeng_plan_s *xeng_plan_t;
+
+enum {
+    XENG_OK = 0,
+    XENG_EINVAL = -1,    /* bad argument: size < 1, NULL pointer, unknown flag */
+    XENG_EPLAN = -2,     /* argument disagrees with the plan (N, F, T > T_max, count) */
+    XENG_EOVERFLOW = -3, /* T > XENG_T_EXACT_MAX: int32 could overflow */
+    XENG_EHIP = -4,      /* HIP runtime or launch error (text: xeng_plan_error) */
+    XENG_ENOMEM = -5     /* host or device workspace allocation failed */
+};
+
+/* Flags of xeng_plan / xeng_plan_batch. */
+enum {
+    XENG_FORM_I8 = 0,        /* int8 MFMA, int32 accumulators (default) */
+    XENG_FORM_F8 = 1,        /* FP8 e4m3 MFMA, f32 accumulators flushed to int32 */
+    XENG_FORM_MASK = 0xff,
+    XENG_ACCUMULATE = 1 << 8 /* add into vis instead of overwriting it */
+};
+
+#define XENG_T_EXACT_MAX 16777215 /* 2^24 - 1 */
+#define XENG_N_MAX 32768          /* inputs per instance, at most */
+#define XENG_F8_FLUSH_MAX 65536   /* FP8 form: samples per f32 partial sum, at most */
+
+/* Library version: (major << 16) | minor. */
+int xeng_version(void);
+
+/* Text of an error code (static storage). */
+const char *xeng_strerror(int code);
+
+/*
+ * Create a plan for frames of N inputs, F channels and at most T_max samples.
+ * flags: one XENG_FORM_* value, optionally | XENG_ACCUMULATE.  The plan does
+ * no HIP call; workspace, if a call needs any, is allocated on first use.
+ * Errors: XENG_EINVAL (out NULL, N, F or T_max < 1, N > XENG_N_MAX, unknown flag bits),
+ * XENG_EOVERFLOW (T_max > XENG_T_EXACT_MAX), XENG_ENOMEM.
+ */
+int xeng_plan(xeng_plan_t *out, int N, int F, int T_max, unsigned flags);
+
+/*
+ * Correlate one frame: vis (see layout above) from samples[T][F][N].
+ * N and F must equal the plan's, 1 <= T <= T_max.  With XENG_ACCUMULATE in the
+ * plan, the frame's sums are added to vis; otherwise vis is overwritten.
+ * Errors: XENG_EINVAL (NULL plan or pointer, T < 1), XENG_EPLAN (N or F differ
+ * from the plan, T > T_max), XENG_EOVERFLOW (T > XENG_T_EXACT_MAX), XENG_EHIP.
+ */
+int xeng_correlate(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
+                   int32_t *vis, void *stream);
+
+/*
+ * Tuning knobs of a plan (0 = choose automatically):
+ *   split_t  number of time slices per tile (1 = one workgroup per tile; more
+ *            slices fill the GPU when there are few tiles, at the price of
+ *            int32 atomic adds into vis, which are exact);
+ *   chunk    reserved, must be 0.
+ * Errors: XENG_EINVAL (NULL plan, negative values).
+ */
+int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int chunk);
+
+/* Free a plan (NULL is accepted).  Waits for nothing: the caller must not
+ * destroy a plan with work still in flight on its stream. */
+int xeng_destroy(xeng_plan_t p);
+
+/* Text of the last XENG_EHIP error seen by this plan ("" if none). */
+const char *xeng_plan_error(xeng_plan_t p);
+
+/* ------------------------------------------------------------------------
+ * Batched form: many independent correlation instances in one launch.
+ * Each instance has its own N, F and T, its own samples and its own vis, laid
+ * out as above.  Channels of different instances never mix: this is the same
+ * definition applied instance by instance.
+ */
+typedef struct xeng_instance {
+    int N;       /* inputs */
+    int F;       /* channels */
+    int T;       /* samples integrated per call */
+    int split_t; /* time slices per tile; 0 = automatic (autotuner output goes here) */
+} xeng_instance;
+
+/*
+ * Plan a batch of `count` instances (copied; descs may be freed after the
+ * call).  flags as for xeng_plan (the form applies to every instance).
+ * The plan owns a device table of work items, built on first use.
+ * Errors: XENG_EINVAL (out or descs NULL, count < 1, any N, F or T < 1,
+ * any N > XENG_N_MAX, negative split_t, unknown flags), XENG_EOVERFLOW (any T > XENG_T_EXACT_MAX),
+ * XENG_ENOMEM.
+ */
+int xeng_plan_batch(xeng_plan_t *out, const xeng_instance *descs, int count, unsigned flags);
+
+/*
+ * Correlate every instance of a batch plan: samples[k] and vis[k] are the
+ * device buffers of instance k (host arrays of count device pointers).  One
+ * persistent kernel launch covers all instances.  Pointers are copied to the
+ * device through plan-owned pinned staging on the given stream.
+ * Errors: XENG_EINVAL (NULL plan or arrays, NULL element), XENG_EPLAN (not a
+ * batch plan), XENG_EHIP, XENG_ENOMEM.
+ */
+int xeng_correlate_batch(xeng_plan_t p, const uint8_t *const *samples, int32_t *const *vis,
+                         void *stream);
+
+/*
+ * As xeng_correlate_batch, replaying a HIP graph captured on the first call
+ * for this exact array of pointers (re-captured when any pointer changes).
+ * For fixed slot buffers, a call is one hipGraphLaunch.
+ */
+int xeng_correlate_batch_graph(xeng_plan_t p, const uint8_t *const *samples,
+                               int32_t *const *vis, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XENG_H */

@@ -47,6 +47,9 @@ def load(mutant: Optional[str] = None, path: Optional[str] = None) -> ctypes.CDL
     lib.oracle_correlate_gated.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip,
                                            ctypes.c_int, i64p]
     lib.oracle_correlate_gated.restype = ctypes.c_int
+    lib.oracle_correlate_pairs.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip, ip,
+                                           ctypes.c_int, i64p]
+    lib.oracle_correlate_pairs.restype = ctypes.c_int
     lib.oracle_threads.restype = ctypes.c_int
     _LIBS[key] = lib
     return lib
@@ -101,6 +104,26 @@ def correlate_gated(samples: np.ndarray, gate: np.ndarray, G: int,
         out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     if rc != 0:
         raise ValueError(f"oracle_correlate_gated failed ({rc})")
+    return out
+
+
+def correlate_pairs(samples: np.ndarray, f: np.ndarray, i: np.ndarray, j: np.ndarray,
+                    lib: Optional[ctypes.CDLL] = None) -> np.ndarray:
+    """V_f[i][j] (int64 re, im) for selected baselines, one by one."""
+    s = np.ascontiguousarray(samples, dtype=np.uint8)
+    T, F, N = s.shape
+    fa, ia, ja = (np.ascontiguousarray(x, dtype=np.int32) for x in (f, i, j))
+    if not (fa.shape == ia.shape == ja.shape) or fa.ndim != 1:
+        raise ValueError("f, i, j must be equal-length 1-D arrays")
+    out = np.zeros((len(fa), 2), dtype=np.int64)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib = lib or load()
+    rc = lib.oracle_correlate_pairs(
+        s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), N, F, T, fa.ctypes.data_as(ip),
+        ia.ctypes.data_as(ip), ja.ctypes.data_as(ip), len(fa),
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise ValueError(f"oracle_correlate_pairs failed ({rc})")
     return out
 
 

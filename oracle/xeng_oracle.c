@@ -185,3 +185,34 @@ int oracle_correlate_gated(const uint8_t *samples, int N, int F, int T,
     }
     return 0;
 }
+
+/*
+ * Selected baselines only: out[k] = V_{f[k]}[i[k]][j[k]] as (re, im), summed
+ * over t in [0, T) straight from the sample bytes (the same definition as
+ * above, one baseline at a time), for checking full-size frames at sampled
+ * outputs.  Any i, j order is accepted (i > j gives the conjugate).
+ */
+int oracle_correlate_pairs(const uint8_t *samples, int N, int F, int T, const int *fs,
+                           const int *is, const int *js, int npairs, int64_t *out) {
+    if (!samples || !fs || !is || !js || !out || N < 1 || F < 1 || T < 0 || npairs < 0)
+        return -1;
+    for (int k = 0; k < npairs; ++k)
+        if (fs[k] < 0 || fs[k] >= F || is[k] < 0 || is[k] >= N || js[k] < 0 || js[k] >= N)
+            return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < npairs; ++k) {
+        const int64_t f = fs[k], i = is[k], j = js[k];
+        int64_t acc_re = 0, acc_im = 0;
+        for (int64_t t = 0; t < T; ++t) {
+            const uint8_t si = samples[(t * F + f) * N + i];
+            const uint8_t sj = samples[(t * F + f) * N + j];
+            const int64_t a = nib_real(si), b = nib_imag(si);
+            const int64_t c = nib_real(sj), d = nib_imag(sj);
+            acc_re += a * c + b * d;
+            acc_im += b * c - a * d;
+        }
+        out[2 * k] = acc_re;
+        out[2 * k + 1] = acc_im;
+    }
+    return 0;
+}

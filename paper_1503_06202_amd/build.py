@@ -1,0 +1,53 @@
+"""Build the X-engine's HIP library ``libxeng.so`` in-tree for gfx950.
+
+The library is one shared object from the HIP kernels and the C ABI in
+``csrc/``; it exports the entry points declared in ``include/xeng.h``.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libxeng.so")
+SOURCES = ("xcorr_kernels.hip", "xeng_api.cpp")
+ARCH = "gfx950"
+
+
+def hipcc() -> str:
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    p = os.path.join(rocm, "bin", "hipcc")
+    return p if os.path.exists(p) else "hipcc"
+
+
+def command(out: str = LIB) -> list:
+    return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-fPIC", "-shared", "-std=c++17",
+            "-Wall", "-Wno-unused-result",
+            # keep the compiler from emitting packed FP32 instructions
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-I", os.path.join(ROOT, "include"),
+            "-o", out] + [os.path.join(CSRC, s) for s in SOURCES]
+
+
+def build(quiet: bool = True) -> str:
+    tmp = LIB + ".tmp"
+    cmd = command(tmp)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    noise = "is not a recognized feature for this target"
+    msg = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)
+    if res.returncode != 0:
+        sys.stderr.write(msg + "\n")
+        raise RuntimeError("libxeng build failed: " + " ".join(cmd))
+    if msg.strip() and not quiet:
+        print(msg)
+    os.replace(tmp, LIB)
+    if not quiet:
+        print("built", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(quiet=False)

@@ -1,0 +1,410 @@
+// C ABI of the X-engine (declared in include/xeng.h): plans, argument checks,
+// launch configuration and the batched form's work lists and graphs.
+//
+// Every check that can fail on arguments runs on the host before the first
+// HIP call, so those errors are reported the same with or without a GPU.
+#include "xeng.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "xeng_internal.hpp"
+
+namespace {
+
+constexpr int kTile = 128;   // tile edge of the kernels
+constexpr int kChunk = 64;   // samples per staged chunk
+constexpr int kOccupancy = 2;  // workgroups per CU (LDS: 64 KiB each)
+
+enum PlanKind { PLAN_SINGLE = 1, PLAN_BATCH = 2 };
+
+}  // namespace
+
+struct xeng_plan_s {
+  int kind = 0;
+  int N = 0, F = 0, T_max = 0;
+  unsigned flags = 0;
+  int form = XENG_FORM_I8;
+  bool accumulate = false;
+  int split_t = 0;  // 0 = automatic
+  int cu_count = 0;
+  std::string err;
+
+  // batched form
+  std::vector<xeng_instance> insts;
+  std::vector<xeng::BatchItem> items;
+  std::vector<int> inst_zero;
+  bool any_zero = false;
+  xeng::BatchInst* h_insts = nullptr;  // pinned staging
+  xeng::BatchInst* d_insts = nullptr;
+  xeng::BatchItem* d_items = nullptr;
+  int* d_counter = nullptr;
+  hipEvent_t copy_done = nullptr;
+  bool copy_pending = false;
+  std::vector<const void*> uploaded;  // pointers now in d_insts
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+int hip_fail(xeng_plan_t p, hipError_t e, const char* what) {
+  if (p) {
+    p->err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  }
+  return XENG_EHIP;
+}
+
+bool flags_ok(unsigned flags) {
+  const unsigned form = flags & XENG_FORM_MASK;
+  if (form != XENG_FORM_I8 && form != XENG_FORM_F8) return false;
+  return (flags & ~(unsigned)(XENG_FORM_MASK | XENG_ACCUMULATE)) == 0;
+}
+
+int ensure_cu_count(xeng_plan_t p) {
+  if (p->cu_count > 0) return XENG_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(p, e, "hipGetDevice");
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return hip_fail(p, e, "hipDeviceGetAttribute");
+  p->cu_count = cus > 0 ? cus : 1;
+  return XENG_OK;
+}
+
+long long tiles_per_channel(int N) {
+  const long long nt = (N + kTile - 1) / kTile;
+  return nt * (nt + 1) / 2;
+}
+
+// Time slices per tile: one when the tiles alone fill the GPU several times
+// over, otherwise enough slices (of at least 4096 samples) to do so.
+int auto_slices(long long tiles, int T, int cu_count) {
+  const long long slots = (long long)cu_count * kOccupancy;
+  if (tiles >= 4 * slots) return 1;
+  long long want = (4 * slots + tiles - 1) / tiles;
+  long long by_t = std::max(1, T / 4096);
+  return (int)std::max(1LL, std::min(want, by_t));
+}
+
+}  // namespace
+
+extern "C" {
+
+int xeng_version(void) { return (1 << 16) | 0; }
+
+const char* xeng_strerror(int code) {
+  switch (code) {
+    case XENG_OK: return "success";
+    case XENG_EINVAL: return "invalid argument";
+    case XENG_EPLAN: return "argument does not match the plan";
+    case XENG_EOVERFLOW: return "integration too long for exact int32 sums";
+    case XENG_EHIP: return "HIP runtime or launch error";
+    case XENG_ENOMEM: return "out of memory";
+    default: return "unknown error code";
+  }
+}
+
+int xeng_plan(xeng_plan_t* out, int N, int F, int T_max, unsigned flags) {
+  if (!out) return XENG_EINVAL;
+  *out = nullptr;
+  if (N < 1 || F < 1 || T_max < 1 || N > XENG_N_MAX || !flags_ok(flags)) return XENG_EINVAL;
+  if (T_max > XENG_T_EXACT_MAX) return XENG_EOVERFLOW;
+  xeng_plan_t p = new (std::nothrow) xeng_plan_s();
+  if (!p) return XENG_ENOMEM;
+  p->kind = PLAN_SINGLE;
+  p->N = N;
+  p->F = F;
+  p->T_max = T_max;
+  p->flags = flags;
+  p->form = (int)(flags & XENG_FORM_MASK);
+  p->accumulate = (flags & XENG_ACCUMULATE) != 0;
+  *out = p;
+  return XENG_OK;
+}
+
+int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int chunk) {
+  if (!p || split_t < 0 || chunk != 0) return XENG_EINVAL;
+  p->split_t = split_t;
+  return XENG_OK;
+}
+
+const char* xeng_plan_error(xeng_plan_t p) { return p ? p->err.c_str() : ""; }
+
+int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, int32_t* vis,
+                   void* stream) {
+  if (!p || !samples || !vis || N < 1 || F < 1 || T < 1) return XENG_EINVAL;
+  if (p->kind != PLAN_SINGLE) return XENG_EPLAN;
+  if (T > XENG_T_EXACT_MAX) return XENG_EOVERFLOW;
+  if (N != p->N || F != p->F || T > p->T_max) return XENG_EPLAN;
+  int rc = ensure_cu_count(p);
+  if (rc != XENG_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+
+  const int nt = (N + kTile - 1) / kTile;
+  const long long tpc = tiles_per_channel(N);
+  const bool aligned = (N % 8 == 0) && ((reinterpret_cast<uintptr_t>(samples) & 7) == 0);
+  // The FP8 form integrates at most XENG_F8_FLUSH_MAX samples per launch (f32
+  // sums stay exact below 2^24); later launches add their int32 sums in
+  // stream order.  The int8 form does the whole frame in one launch.
+  const int seg = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : T;
+  for (int t0 = 0; t0 < T; t0 += seg) {
+    const int t1 = std::min(T, t0 + seg), len = t1 - t0;
+    int nslices = p->split_t > 0 ? p->split_t : auto_slices(tpc * F, len, p->cu_count);
+    nslices = std::min(nslices, (len + kChunk - 1) / kChunk);
+    int slice_len = (len + nslices - 1) / nslices;
+    slice_len = (slice_len + kChunk - 1) / kChunk * kChunk;
+    nslices = (len + slice_len - 1) / slice_len;
+    const bool add = p->accumulate || t0 > 0;
+
+    xeng::TileArgs a;
+    a.samples = samples;
+    a.vis = vis;
+    a.N = N;
+    a.F = F;
+    a.t0 = t0;
+    a.t1 = t1;
+    a.nt = nt;
+    a.tiles_per_chan = (int)tpc;
+    a.nslices = nslices;
+    a.slice_len = slice_len;
+    a.row_stride = (long long)F * N;
+    if (nslices > 1) {
+      a.write_mode = xeng::WM_ATOMIC;
+      if (!add) {
+        hipError_t e = xeng::launch_zero(vis, (long long)F * N * (N + 1), s);
+        if (e != hipSuccess) return hip_fail(p, e, "zero fill launch");
+      }
+    } else {
+      a.write_mode = add ? xeng::WM_ADD : xeng::WM_STORE;
+    }
+    hipError_t e = xeng::launch_tiles(a, p->form, aligned, s);
+    if (e != hipSuccess) return hip_fail(p, e, "correlation kernel launch");
+  }
+  return XENG_OK;
+}
+
+int xeng_plan_batch(xeng_plan_t* out, const xeng_instance* descs, int count, unsigned flags) {
+  if (!out) return XENG_EINVAL;
+  *out = nullptr;
+  if (!descs || count < 1 || !flags_ok(flags)) return XENG_EINVAL;
+  for (int k = 0; k < count; ++k) {
+    const xeng_instance& d = descs[k];
+    if (d.N < 1 || d.F < 1 || d.T < 1 || d.N > XENG_N_MAX || d.split_t < 0) return XENG_EINVAL;
+  }
+  for (int k = 0; k < count; ++k)
+    if (descs[k].T > XENG_T_EXACT_MAX) return XENG_EOVERFLOW;
+  xeng_plan_t p = new (std::nothrow) xeng_plan_s();
+  if (!p) return XENG_ENOMEM;
+  p->kind = PLAN_BATCH;
+  p->flags = flags;
+  p->form = (int)(flags & XENG_FORM_MASK);
+  p->accumulate = (flags & XENG_ACCUMULATE) != 0;
+  try {
+    p->insts.assign(descs, descs + count);
+    p->inst_zero.assign(count, 0);
+    struct Costed {
+      long long cost;
+      xeng::BatchItem it;
+    };
+    std::vector<Costed> work;
+    for (int k = 0; k < count; ++k) {
+      const xeng_instance& d = descs[k];
+      const int nt = (d.N + kTile - 1) / kTile;
+      int S = d.split_t > 0 ? d.split_t : 1;
+      // FP8: no slice may integrate more than XENG_F8_FLUSH_MAX samples
+      if (p->form == XENG_FORM_F8)
+        S = std::max(S, (d.T + XENG_F8_FLUSH_MAX - 1) / XENG_F8_FLUSH_MAX);
+      S = std::min(S, (d.T + kChunk - 1) / kChunk);
+      int len = (d.T + S - 1) / S;
+      len = (len + kChunk - 1) / kChunk * kChunk;
+      S = (d.T + len - 1) / len;
+      const int mode = S > 1 ? xeng::WM_ATOMIC : (p->accumulate ? xeng::WM_ADD : xeng::WM_STORE);
+      if (S > 1 && !p->accumulate) {
+        p->inst_zero[k] = 1;
+        p->any_zero = true;
+      }
+      for (int f = 0; f < d.F; ++f)
+        for (int I = 0; I < nt; ++I)
+          for (int J = I; J < nt; ++J)
+            for (int s = 0; s < S; ++s) {
+              xeng::BatchItem it;
+              it.inst = k;
+              it.f = f;
+              it.I = I;
+              it.J = J;
+              it.t0 = s * len;
+              it.t1 = std::min(d.T, (s + 1) * len);
+              it.mode = mode;
+              it.pad = 0;
+              // cost: MFMA blocks that hold baselines x samples
+              const int rows = std::min(kTile, d.N - I * kTile);
+              const int cols = std::min(kTile, d.N - J * kTile);
+              long long area = I == J ? (long long)rows * (rows + 1) / 2 : (long long)rows * cols;
+              work.push_back({area * (it.t1 - it.t0), it});
+            }
+    }
+    std::stable_sort(work.begin(), work.end(),
+                     [](const Costed& x, const Costed& y) { return x.cost > y.cost; });
+    p->items.reserve(work.size());
+    for (const Costed& c : work) p->items.push_back(c.it);
+  } catch (const std::bad_alloc&) {
+    delete p;
+    return XENG_ENOMEM;
+  }
+  if (p->items.size() > 0x7fffffffu) {
+    delete p;
+    return XENG_EINVAL;
+  }
+  *out = p;
+  return XENG_OK;
+}
+
+static int batch_setup(xeng_plan_t p) {
+  if (p->d_items) return XENG_OK;
+  int rc = ensure_cu_count(p);
+  if (rc != XENG_OK) return rc;
+  const size_t ni = p->insts.size(), nw = p->items.size();
+  hipError_t e = hipHostMalloc((void**)&p->h_insts, ni * sizeof(xeng::BatchInst), hipHostMallocDefault);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? XENG_ENOMEM : hip_fail(p, e, "hipHostMalloc");
+  e = hipMalloc((void**)&p->d_insts, ni * sizeof(xeng::BatchInst));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, nw * sizeof(xeng::BatchItem));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_counter, sizeof(int));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? XENG_ENOMEM : hip_fail(p, e, "hipMalloc");
+  e = hipMemcpy(p->d_items, p->items.data(), nw * sizeof(xeng::BatchItem), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(p, e, "work list upload");
+  e = hipEventCreateWithFlags(&p->copy_done, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(p, e, "hipEventCreate");
+  return XENG_OK;
+}
+
+// Bring the device instance table up to date with these pointers (a no-op
+// when they are the ones already uploaded).
+static int batch_upload(xeng_plan_t p, const uint8_t* const* samples, int32_t* const* vis,
+                        hipStream_t s) {
+  const size_t ni = p->insts.size();
+  bool same = p->uploaded.size() == 2 * ni;
+  for (size_t k = 0; same && k < ni; ++k)
+    same = p->uploaded[2 * k] == samples[k] && p->uploaded[2 * k + 1] == vis[k];
+  if (same) return XENG_OK;
+  if (p->copy_pending) {
+    // the pinned staging may still be read by the previous call's copy
+    hipError_t e = hipEventSynchronize(p->copy_done);
+    if (e != hipSuccess) return hip_fail(p, e, "hipEventSynchronize");
+    p->copy_pending = false;
+  }
+  p->uploaded.assign(2 * ni, nullptr);
+  for (size_t k = 0; k < ni; ++k) {
+    const xeng_instance& d = p->insts[k];
+    xeng::BatchInst& b = p->h_insts[k];
+    b.samples = samples[k];
+    b.vis = vis[k];
+    b.N = d.N;
+    b.F = d.F;
+    b.T = d.T;
+    b.aligned = (d.N % 8 == 0) && ((reinterpret_cast<uintptr_t>(samples[k]) & 7) == 0);
+    b.zero = p->inst_zero[k];
+    b.pad = 0;
+    p->uploaded[2 * k] = samples[k];
+    p->uploaded[2 * k + 1] = vis[k];
+  }
+  hipError_t e = hipMemcpyAsync(p->d_insts, p->h_insts, ni * sizeof(xeng::BatchInst),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(p->copy_done, s);
+  if (e != hipSuccess) {
+    p->uploaded.clear();
+    return hip_fail(p, e, "instance table upload");
+  }
+  p->copy_pending = true;
+  return XENG_OK;
+}
+
+static int batch_check(xeng_plan_t p, const uint8_t* const* samples, int32_t* const* vis) {
+  if (!p || !samples || !vis) return XENG_EINVAL;
+  if (p->kind != PLAN_BATCH) return XENG_EPLAN;
+  for (size_t k = 0; k < p->insts.size(); ++k)
+    if (!samples[k] || !vis[k]) return XENG_EINVAL;
+  return XENG_OK;
+}
+
+static int batch_grid(xeng_plan_t p) {
+  const long long g = std::min<long long>((long long)p->cu_count * kOccupancy,
+                                          (long long)p->items.size());
+  return (int)std::max(1LL, g);
+}
+
+int xeng_correlate_batch(xeng_plan_t p, const uint8_t* const* samples, int32_t* const* vis,
+                         void* stream) {
+  int rc = batch_check(p, samples, vis);
+  if (rc != XENG_OK) return rc;
+  rc = batch_setup(p);
+  if (rc != XENG_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = batch_upload(p, samples, vis, s);
+  if (rc != XENG_OK) return rc;
+  hipError_t e = xeng::launch_batch(p->d_insts, (int)p->insts.size(), p->d_items,
+                                    (int)p->items.size(), p->d_counter, batch_grid(p), p->form,
+                                    p->any_zero, s);
+  if (e != hipSuccess) return hip_fail(p, e, "batch kernel launch");
+  return XENG_OK;
+}
+
+int xeng_correlate_batch_graph(xeng_plan_t p, const uint8_t* const* samples,
+                               int32_t* const* vis, void* stream) {
+  int rc = batch_check(p, samples, vis);
+  if (rc != XENG_OK) return rc;
+  rc = batch_setup(p);
+  if (rc != XENG_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  rc = batch_upload(p, samples, vis, s);
+  if (rc != XENG_OK) return rc;
+  if (!p->graph_exec) {
+    // The kernels read every pointer from the device instance table, so one
+    // captured graph serves every set of buffers.
+    hipError_t e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(p, e, "hipStreamCreate");
+    e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(p, e, "hipStreamBeginCapture");
+    hipError_t le = xeng::launch_batch(p->d_insts, (int)p->insts.size(), p->d_items,
+                                       (int)p->items.size(), p->d_counter, batch_grid(p),
+                                       p->form, p->any_zero, p->capture_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->capture_stream, &g);
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return hip_fail(p, le, "batch kernel capture");
+    }
+    if (e != hipSuccess) return hip_fail(p, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      p->graph_exec = nullptr;
+      return hip_fail(p, e, "hipGraphInstantiate");
+    }
+  }
+  hipError_t e = hipGraphLaunch(p->graph_exec, s);
+  if (e != hipSuccess) return hip_fail(p, e, "hipGraphLaunch");
+  return XENG_OK;
+}
+
+int xeng_destroy(xeng_plan_t p) {
+  if (!p) return XENG_OK;
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  if (p->copy_done) (void)hipEventDestroy(p->copy_done);
+  if (p->d_insts) (void)hipFree(p->d_insts);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_counter) (void)hipFree(p->d_counter);
+  if (p->h_insts) (void)hipHostFree(p->h_insts);
+  delete p;
+  return XENG_OK;
+}
+
+}  // extern "C"

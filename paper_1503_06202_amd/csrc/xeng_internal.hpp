@@ -1,0 +1,55 @@
+// Internal interface between the C ABI (xeng_api.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xeng {
+
+// How a finished tile reaches vis: plain store, read-add-store (the
+// workgroup owns the tile), or int32 atomic add (several workgroups share it).
+enum WriteMode { WM_STORE = 0, WM_ADD = 1, WM_ATOMIC = 2 };
+
+// Arguments of the tile kernel: one frame, all channels.
+struct TileArgs {
+  const uint8_t* samples;  // device [T][F][N]
+  int32_t* vis;            // device [F][N(N+1)/2][2]
+  int N, F;
+  int t0, t1;          // integrated time range [t0, t1) of this launch
+  int nt;              // tiles per edge, ceil(N / 128)
+  int tiles_per_chan;  // nt (nt + 1) / 2
+  int nslices;         // time slices per tile
+  int slice_len;       // samples per slice, a multiple of 64
+  int write_mode;      // WM_STORE, WM_ADD or WM_ATOMIC
+  long long row_stride;  // F * N: bytes between consecutive time rows
+};
+
+hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t stream);
+hipError_t launch_zero(int32_t* p, long long n, hipStream_t stream);
+
+// One work item of the batched persistent kernel.
+struct BatchItem {
+  int inst;   // instance index
+  int f;      // channel
+  int I, J;   // tile
+  int t0, t1; // time range
+  int mode;   // write mode
+  int pad;
+};
+
+// Per-instance descriptor on the device.
+struct BatchInst {
+  const uint8_t* samples;  // device [T][F][N]
+  int32_t* vis;            // device [F][N(N+1)/2][2]
+  int N, F, T;
+  int aligned;  // N % 8 == 0 and samples 8-byte aligned
+  int zero;     // clear vis before the launch (its tiles are integrated by atomic adds)
+  int pad;
+};
+
+// Clear the outputs flagged `zero` and reset the work counter, then run the
+// persistent kernel with `grid` workgroups over the item list.
+hipError_t launch_batch(const BatchInst* insts, int ninst, const BatchItem* items, int nitems,
+                        int* counter, int grid, int form, bool any_zero, hipStream_t stream);
+
+}  // namespace xeng

@@ -1,0 +1,186 @@
+"""Python face of the X-engine: plans over torch device tensors.
+
+torch provides device memory and streams; the correlation itself runs in
+``libxeng.so`` (HIP kernels for gfx950) through the C ABI of
+``include/xeng.h``.  There is no CPU path: without the library, or without a
+GPU, calls raise.
+
+Layouts (Sec. II-A footnote for the sample code; Eq. (1) for the baseline
+count):
+  samples  uint8  [T][F][N], high nibble = Re + 8, low nibble = Im + 8
+  vis      int32  [F][N(N+1)/2][2], row-major upper triangle, (re, im)
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib
+from ._lib import XengError  # noqa: F401
+
+FORMS = {"i8": _lib.XENG_FORM_I8, "f8": _lib.XENG_FORM_F8}
+
+
+def num_baselines(N: int) -> int:
+    """N(N+1)/2: all pairs of inputs including autocorrelations (Eq. (1))."""
+    return N * (N + 1) // 2
+
+
+def vis_shape(N: int, F: int) -> Tuple[int, int, int]:
+    return (F, num_baselines(N), 2)
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _check_samples(samples: torch.Tensor) -> Tuple[int, int, int]:
+    if samples.dtype != torch.uint8 or samples.dim() != 3:
+        raise ValueError("samples must be a uint8 tensor [T][F][N]")
+    if not samples.is_cuda:
+        raise ValueError("samples must be on the GPU")
+    if not samples.is_contiguous():
+        raise ValueError("samples must be contiguous")
+    T, F, N = samples.shape
+    return int(T), int(F), int(N)
+
+
+def _check_vis(vis: torch.Tensor, N: int, F: int, device) -> None:
+    if vis.dtype != torch.int32 or tuple(vis.shape) != vis_shape(N, F):
+        raise ValueError(f"vis must be int32 {vis_shape(N, F)}")
+    if not vis.is_cuda or not vis.is_contiguous() or vis.device != device:
+        raise ValueError("vis must be a contiguous tensor on the samples' GPU")
+
+
+class Plan:
+    """A correlation plan for frames of N inputs, F channels, T <= T_max samples.
+
+    ``form`` is "i8" (int8 MFMA, int32 accumulators) or "f8" (FP8 e4m3 MFMA,
+    f32 partial sums flushed to int32 every <= 65536 samples).  With
+    ``accumulate`` the frame's sums are added to ``vis``.
+    """
+
+    def __init__(self, N: int, F: int, T_max: int, form: str = "i8", accumulate: bool = False,
+                 split_t: int = 0):
+        if form not in FORMS:
+            raise ValueError(f"form must be one of {sorted(FORMS)}")
+        self.N, self.F, self.T_max, self.form, self.accumulate = N, F, T_max, form, accumulate
+        flags = FORMS[form] | (_lib.XENG_ACCUMULATE if accumulate else 0)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().xeng_plan(ctypes.byref(h), int(N), int(F), int(T_max), flags),
+                   "xeng_plan")
+        self._h = h
+        if split_t:
+            self.set_tuning(split_t)
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def set_tuning(self, split_t: int = 0) -> None:
+        _lib.check(_lib.lib().xeng_plan_set_tuning(self._h, int(split_t), 0),
+                   "xeng_plan_set_tuning")
+
+    def correlate(self, samples: torch.Tensor, vis: Optional[torch.Tensor] = None,
+                  stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """Visibilities of ``samples`` [T][F][N] (asynchronous on ``stream``)."""
+        T, F, N = _check_samples(samples)
+        if vis is None:
+            if self.accumulate:
+                raise ValueError("an accumulating plan needs the vis to add into")
+            vis = torch.empty(vis_shape(N, F), dtype=torch.int32, device=samples.device)
+        else:
+            _check_vis(vis, N, F, samples.device)
+        rc = _lib.lib().xeng_correlate(self._h, samples.data_ptr(), N, F, T, vis.data_ptr(),
+                                       _stream_handle(stream))
+        _lib.check(rc, "xeng_correlate", self._h.value)
+        return vis
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().xeng_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def correlate(samples: torch.Tensor, form: str = "i8", vis: Optional[torch.Tensor] = None,
+              accumulate: bool = False, split_t: int = 0,
+              stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """One-shot correlation of a frame (plans, runs and frees a plan)."""
+    T, F, N = _check_samples(samples)
+    with Plan(N, F, T, form=form, accumulate=accumulate, split_t=split_t) as p:
+        return p.correlate(samples, vis, stream)
+
+
+class BatchPlan:
+    """Many independent (N, F, T) instances correlated by one persistent launch."""
+
+    def __init__(self, instances: Sequence[Tuple[int, int, int]], form: str = "i8",
+                 accumulate: bool = False, split_t: Optional[Sequence[int]] = None):
+        if form not in FORMS:
+            raise ValueError(f"form must be one of {sorted(FORMS)}")
+        self.instances: List[Tuple[int, int, int]] = [tuple(map(int, x)) for x in instances]
+        self.form, self.accumulate = form, accumulate
+        n = len(self.instances)
+        splits = list(split_t) if split_t is not None else [0] * n
+        if len(splits) != n:
+            raise ValueError("one split_t per instance")
+        arr = (_lib.XengInstance * max(1, n))()
+        for k, ((N, F, T), s) in enumerate(zip(self.instances, splits)):
+            arr[k] = _lib.XengInstance(N, F, T, int(s))
+        flags = FORMS[form] | (_lib.XENG_ACCUMULATE if accumulate else 0)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().xeng_plan_batch(ctypes.byref(h), arr, n, flags), "xeng_plan_batch")
+        self._h = h
+        self._keep = None
+
+    def _arrays(self, samples: Sequence[torch.Tensor], vis: Sequence[torch.Tensor]):
+        n = len(self.instances)
+        if len(samples) != n or len(vis) != n:
+            raise ValueError(f"need {n} sample and vis tensors")
+        for k, (N, F, T) in enumerate(self.instances):
+            Ts, Fs, Ns = _check_samples(samples[k])
+            if (Ts, Fs, Ns) != (T, F, N):
+                raise ValueError(f"instance {k}: samples shape {(Ts, Fs, Ns)} != planned {(T, F, N)}")
+            _check_vis(vis[k], N, F, samples[k].device)
+        sp = (ctypes.c_void_p * n)(*[s.data_ptr() for s in samples])
+        vp = (ctypes.c_void_p * n)(*[v.data_ptr() for v in vis])
+        return sp, vp
+
+    def correlate(self, samples: Sequence[torch.Tensor], vis: Sequence[torch.Tensor],
+                  stream: Optional[torch.cuda.Stream] = None, graph: bool = False) -> None:
+        sp, vp = self._arrays(samples, vis)
+        fn = _lib.lib().xeng_correlate_batch_graph if graph else _lib.lib().xeng_correlate_batch
+        rc = fn(self._h, sp, vp, _stream_handle(stream))
+        _lib.check(rc, "xeng_correlate_batch", self._h.value)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().xeng_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

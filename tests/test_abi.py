@@ -1,0 +1,127 @@
+"""The C-ABI library: it loads, exports every declared symbol, and rejects bad
+arguments on the host before any HIP call (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1503_06202_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xeng.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xeng_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return _lib.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_version_and_strerror(L):
+    assert L.xeng_version() >> 16 == 1
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.xeng_strerror(code)
+    assert L.xeng_strerror(-99) == b"unknown error code"
+
+
+def _plan(L, N, F, T, flags=0):
+    h = ctypes.c_void_p()
+    rc = L.xeng_plan(ctypes.byref(h), N, F, T, flags)
+    return rc, h
+
+
+def test_plan_validation(L):
+    assert L.xeng_plan(None, 4, 1, 1, 0) == _lib.XENG_EINVAL
+    for N, F, T in ((0, 1, 1), (1, 0, 1), (1, 1, 0), (-5, 1, 1), (_lib.XENG_N_MAX + 1, 1, 1)):
+        rc, h = _plan(L, N, F, T)
+        assert rc == _lib.XENG_EINVAL and not h.value
+    rc, h = _plan(L, 4, 1, _lib.XENG_T_EXACT_MAX + 1)
+    assert rc == _lib.XENG_EOVERFLOW
+    for bad in (2, 0x200, 1 << 20, 0xFF):
+        rc, h = _plan(L, 4, 1, 16, bad)
+        assert rc == _lib.XENG_EINVAL, bad
+    rc, h = _plan(L, _lib.XENG_N_MAX, 3, _lib.XENG_T_EXACT_MAX, _lib.XENG_FORM_F8 | _lib.XENG_ACCUMULATE)
+    assert rc == _lib.XENG_OK and h.value
+    assert L.xeng_destroy(h) == 0
+    assert L.xeng_destroy(None) == 0
+
+
+def test_correlate_validation_needs_no_gpu(L):
+    rc, h = _plan(L, 64, 2, 1000)
+    assert rc == 0
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation
+    try:
+        assert L.xeng_correlate(None, dummy, 64, 2, 10, dummy, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate(h, None, 64, 2, 10, dummy, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate(h, dummy, 64, 2, 10, None, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate(h, dummy, 64, 2, 0, dummy, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate(h, dummy, 65, 2, 10, dummy, None) == _lib.XENG_EPLAN
+        assert L.xeng_correlate(h, dummy, 64, 3, 10, dummy, None) == _lib.XENG_EPLAN
+        assert L.xeng_correlate(h, dummy, 64, 2, 1001, dummy, None) == _lib.XENG_EPLAN
+        assert L.xeng_correlate(h, dummy, 64, 2, 1 << 24, dummy, None) == _lib.XENG_EOVERFLOW
+        assert L.xeng_plan_set_tuning(h, -1, 0) == _lib.XENG_EINVAL
+        assert L.xeng_plan_set_tuning(h, 3, 1) == _lib.XENG_EINVAL
+        assert L.xeng_plan_set_tuning(h, 3, 0) == _lib.XENG_OK
+        assert L.xeng_plan_error(h) == b""
+    finally:
+        L.xeng_destroy(h)
+
+
+def test_batch_validation_needs_no_gpu(L):
+    def plan(descs, flags=0):
+        arr = (_lib.XengInstance * len(descs))(*[_lib.XengInstance(*d) for d in descs])
+        h = ctypes.c_void_p()
+        return L.xeng_plan_batch(ctypes.byref(h), arr, len(descs), flags), h
+
+    assert plan([(0, 1, 1, 0)])[0] == _lib.XENG_EINVAL
+    assert plan([(8, 1, 1, -1)])[0] == _lib.XENG_EINVAL
+    assert plan([(8, 1, 1 << 24, 0)])[0] == _lib.XENG_EOVERFLOW
+    assert plan([(8, 1, 8, 0)], flags=7)[0] == _lib.XENG_EINVAL
+    h = ctypes.c_void_p()
+    assert L.xeng_plan_batch(ctypes.byref(h), None, 1, 0) == _lib.XENG_EINVAL
+    rc, hb = plan([(64, 4, 8192, 0), (33, 1, 100, 3)])
+    assert rc == 0 and hb.value
+    dummy = ctypes.c_void_p(0x1000)
+    try:
+        arr = (ctypes.c_void_p * 2)(dummy, None)
+        assert L.xeng_correlate_batch(hb, arr, arr, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate_batch(hb, None, arr, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate_batch_graph(hb, arr, arr, None) == _lib.XENG_EINVAL
+        # a single plan is not a batch plan, and the other way round
+        rc, hs = _plan(L, 8, 1, 8)
+        ok = (ctypes.c_void_p * 2)(dummy, dummy)
+        assert L.xeng_correlate_batch(hs, ok, ok, None) == _lib.XENG_EPLAN
+        assert L.xeng_correlate(hb, dummy, 64, 4, 10, dummy, None) == _lib.XENG_EPLAN
+        L.xeng_destroy(hs)
+    finally:
+        L.xeng_destroy(hb)
+
+
+def test_python_layer_fails_loudly_without_library(monkeypatch):
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "LIB_PATH", "/nonexistent/libxeng.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.lib()
+
+
+def test_python_layer_rejects_cpu_tensors():
+    import torch
+    from paper_1503_06202_amd import engine
+    with pytest.raises(ValueError):
+        engine._check_samples(torch.zeros((4, 1, 8), dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        engine._check_samples(torch.zeros((4, 8), dtype=torch.uint8))

@@ -55,3 +55,16 @@ def test_tri_index_matches_triu_order():
     N = 9
     iu, ju = np.triu_indices(N)
     assert [oracle.tri_index(int(i), int(j), N) for i, j in zip(iu, ju)] == list(range(len(iu)))
+
+
+def test_pairs_agree_with_full(oracle_lib):
+    """The one-baseline-at-a-time entry equals the full-channel result (both orders of i, j)."""
+    rng = np.random.default_rng(4)
+    T, F, N = 77, 3, 11
+    s = rng.integers(0, 256, (T, F, N), dtype=np.uint8)
+    full = oracle.correlate(s, full=True, lib=oracle_lib)
+    f = rng.integers(0, F, 200)
+    i = rng.integers(0, N, 200)
+    j = rng.integers(0, N, 200)
+    got = oracle.correlate_pairs(s, f, i, j, lib=oracle_lib)
+    assert np.array_equal(got, full[f, i, j])
