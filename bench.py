@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--form", default="i8", choices=["i8", "f8"])
     ap.add_argument("--split-t", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of the frame's size (a known byte "
+                         "count for scaling the HBM counters of a profiler run)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
     return ap.parse_args()
@@ -148,6 +151,12 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic},
     }
+    if args.calibrate_copy:
+        dst = torch.empty_like(d)
+        dst.copy_(d)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = 2 * d.numel()
+        del dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frame, w)
     plan.close()

@@ -11,32 +11,39 @@
 
 namespace xeng {
 
-// One 64-sample chunk of an 8 x 8 block: raw[k] holds the bytes of inputs
-// n0..n0+7 at time t0 + k (x: n0..n0+3, y: n0+4..n0+7).
-template <bool ALIGNED>
-__device__ __forceinline__ void load_chunk(uint2 (&raw)[8], const uint8_t* __restrict__ samples,
-                                           long long row_stride, int f, int N, int n0, int t0,
-                                           int t_end, bool active) {
+// Inputs of one staging thread: an 8 x 8 byte block, inputs n0..n0+7 at times
+// t0..t0+7 of one channel; raw[k] holds time t0 + k (x: n0..n0+3, y: n0+4..n0+7).
+//
+// Fast path: the whole block lies inside the frame and rows are 8-byte aligned.
+// The row pointer is uniform across the workgroup plus a per-lane 32-bit
+// offset, so the loads need no per-load vector address arithmetic.
+__device__ __forceinline__ void load_block_fast(uint2 (&raw)[8], const uint8_t* __restrict__ rows,
+                                                long long row_stride, uint32_t lane_off) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    raw[k] = *reinterpret_cast<const uint2*>(rows + k * row_stride + lane_off);
+}
+
+// General path (frame edges, unaligned rows): byte loads, absent samples and
+// inputs read as the code of 0 + 0i.
+__device__ __forceinline__ void load_block_edge(uint2 (&raw)[8], const uint8_t* __restrict__ samples,
+                                                long long row_stride, int f, int N, int n0, int t0,
+                                                int t_end, bool active) {
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const int t = t0 + k;
-    raw[k] = make_uint2(0x88888888u, 0x88888888u);  // the code of 0 + 0i
-    if (active && t < t_end && n0 < N) {
+    uint32_t w[2] = {0x88888888u, 0x88888888u};
+    if (active && t < t_end) {
       const uint8_t* p = samples + (long long)t * row_stride + (long long)f * N + n0;
-      if (ALIGNED) {
-        raw[k] = *reinterpret_cast<const uint2*>(p);
-      } else {
-        uint32_t w[2] = {0x88888888u, 0x88888888u};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          if (n0 + e < N) {
-            const uint32_t sh = 8 * (e & 3);
-            w[e >> 2] = (w[e >> 2] & ~(0xFFu << sh)) | ((uint32_t)p[e] << sh);
-          }
+      for (int e = 0; e < 8; ++e) {
+        if (n0 + e < N) {
+          const uint32_t sh = 8 * (e & 3);
+          w[e >> 2] = (w[e >> 2] & ~(0xFFu << sh)) | ((uint32_t)p[e] << sh);
         }
-        raw[k] = make_uint2(w[0], w[1]);
       }
     }
+    raw[k] = make_uint2(w[0], w[1]);
   }
 }
 
@@ -77,63 +84,60 @@ struct Acc<FORM_F8> {
 };
 
 // One chunk of MFMAs for a wave's 64 x 64 sub-tile (2 x 2 blocks of 32 x 32).
-// mask bit (2a + b) enables block (a, b).
+// offA[a] / offB[b]: LDS byte offsets of this lane's rows (a = 0, 1 and
+// b = 0, 1) in the I and J blocks of the current buffer, including the
+// lane-half's first segment; k-step s adds a constant.
 template <int FORM>
-__device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ ldsI,
-                                              const uint8_t* __restrict__ ldsJ, int ra, int rb,
-                                              int half, int mask,
+__device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, const int (&offA)[2],
+                                              const int (&offB)[2],
                                               typename Acc<FORM>::T (&re)[2][2],
                                               typename Acc<FORM>::T (&im)[2][2]) {
   if (FORM == FORM_I8) {
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
-      const int q = 2 * s + half;
       v4i A[2], B[2], Y[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) A[a] = *reinterpret_cast<const v4i*>(ldsI + seg_off(ra + 32 * a, q));
+      for (int a = 0; a < 2; ++a) A[a] = *reinterpret_cast<const v4i*>(lds + offA[a] + 32 * s);
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        B[b] = *reinterpret_cast<const v4i*>(ldsJ + seg_off(rb + 32 * b, q));
+        B[b] = *reinterpret_cast<const v4i*>(lds + offB[b] + 32 * s);
         // [r r m m] -> [-m -m r r]
         Y[b] = v4i{(int)neg_i8((uint32_t)B[b].z), (int)neg_i8((uint32_t)B[b].w), B[b].x, B[b].y};
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-          if (mask & (1 << (2 * a + b))) {
-            re[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], B[b], re[a][b], 0, 0, 0);
-            im[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], Y[b], im[a][b], 0, 0, 0);
-          }
+        for (int b = 0; b < 2; ++b) {
+          re[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], B[b], re[a][b], 0, 0, 0);
+          im[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], Y[b], im[a][b], 0, 0, 0);
+        }
     }
   } else {
 #pragma unroll
     for (int s = 0; s < KC / 32; ++s) {
-      const int q0 = 4 * s + 2 * half;
       v8i A[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const v4i x0 = *reinterpret_cast<const v4i*>(ldsI + seg_off(ra + 32 * a, q0));
-        const v4i x1 = *reinterpret_cast<const v4i*>(ldsI + seg_off(ra + 32 * a, q0 + 1));
+        const v4i x0 = *reinterpret_cast<const v4i*>(lds + offA[a] + 64 * s);
+        const v4i x1 = *reinterpret_cast<const v4i*>(lds + offA[a] + 64 * s + 16);
         A[a] = v8i{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const v4i x0 = *reinterpret_cast<const v4i*>(ldsJ + seg_off(rb + 32 * b, q0));
-        const v4i x1 = *reinterpret_cast<const v4i*>(ldsJ + seg_off(rb + 32 * b, q0 + 1));
+        const v4i x0 = *reinterpret_cast<const v4i*>(lds + offB[b] + 64 * s);
+        const v4i x1 = *reinterpret_cast<const v4i*>(lds + offB[b] + 64 * s + 16);
         const v8i B = v8i{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
         // FP8 negation flips the sign bit: [r r m m] -> [-m -m r r]
         const int sg = (int)0x80808080u;
         const v8i Y = v8i{x0.z ^ sg, x0.w ^ sg, x0.x, x0.y, x1.z ^ sg, x1.w ^ sg, x1.x, x1.y};
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-          if (mask & (1 << (2 * a + b))) {
-            // format 0 = FP8 e4m3 for both operands; scale exponent 127 = 2^0
-            re[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[a], B, re[a][b], 0, 0, 0,
-                                                                       127, 0, 127);
-            im[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[a], Y, im[a][b], 0, 0, 0,
-                                                                       127, 0, 127);
-          }
+        for (int a = 0; a < 2; ++a) {
+          // format 0 = FP8 e4m3 for both operands; scale exponent 127 = 2^0
+          re[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[a], B, re[a][b], 0, 0, 0,
+                                                                     127, 0, 127);
+          im[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[a], Y, im[a][b], 0, 0, 0,
+                                                                     127, 0, 127);
+        }
       }
     }
   }
@@ -198,23 +202,77 @@ __device__ __forceinline__ void tile_of(int p, int nt, int& I, int& J) {
   J = i + (p - (i * nt - i * (i - 1) / 2));
 }
 
+// Everything one thread needs to stage and compute chunks of a tile.
+template <int FORM>
+struct TileCtx {
+  uint8_t* lds;
+  const uint8_t* rows;  // channel's rows at the tile's first sample (uniform)
+  long long row_stride;
+  uint32_t lane_off;    // this thread's loads: 8*tg rows down, input n0
+  int sblk, ng, tg;     // staging role
+  int offA[2], offB[2];
+  typename Acc<FORM>::T re[2][2], im[2][2];
+};
+
+// One chunk of the steady state: optionally load chunk `ld_chunk` into `ld`,
+// compute the chunk staged in `cur`, optionally stage `stg` into `nxt`, then
+// synchronise.  Straight-line code, so that the compiler can interleave the
+// staging arithmetic with the matrix instructions.
+template <int FORM, bool COMPUTE, bool LOAD, bool STAGE>
+__device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, uint2 (&stg)[8],
+                                            uint2 (&ld)[8], int ld_chunk) {
+  if (LOAD)
+    load_block_fast(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride,
+                    x.lane_off);
+  // keep the loads at the top of the step: they have a whole step to land
+  __builtin_amdgcn_sched_barrier(0);
+  if (COMPUTE) compute_chunk<FORM>(x.lds + cur, x.offA, x.offB, x.re, x.im);
+  if (STAGE) stage_chunk<FORM>(stg, x.lds + nxt + x.sblk * BLOCK_LDS, 8 * x.ng, x.tg);
+  __syncthreads();
+}
+
+// Chunks [0, nsteady) of a tile, nsteady even and >= 2, all of whose loads
+// lie inside the frame (chunks < nfast).  Chunk c computes from buffer c & 1
+// while chunk c + 1 is staged into the other buffer and chunk c + 2 loads
+// (two register sets of raw samples).  Prefetches past the last fast chunk
+// reload that chunk, and what they stage is never computed, so the loop body
+// has no branch.
+template <int FORM, bool COMPUTE>
+__device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int nfast) {
+  constexpr int B0 = 0, B1 = STAGE_LDS;
+  uint2 rawA[8], rawB[8];
+  load_block_fast(rawA, x.rows, x.row_stride, x.lane_off);
+  stage_chunk<FORM>(rawA, x.lds + B0 + x.sblk * BLOCK_LDS, 8 * x.ng, x.tg);
+  load_block_fast(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.lane_off);
+  __syncthreads();
+  for (int c = 0; c < nsteady; c += 2) {
+    steady_step<FORM, COMPUTE, true, true>(x, B0, B1, rawA, rawB, min(c + 2, nfast - 1));
+    steady_step<FORM, COMPUTE, true, true>(x, B1, B0, rawB, rawA, min(c + 3, nfast - 1));
+  }
+}
+
 // The work of one tile: baselines [I*128, I*128+128) x [J*128, J*128+128) of
 // channel f, integrated over samples [t_begin, t_end).  All 256 threads call
 // it; it ends with the tile written (mode) and the LDS free for reuse.
 // FP8 form: the caller keeps t_end - t_begin <= 65536, so that every f32
 // partial sum is an integer of magnitude <= 128 * 65536 = 2^23 (exact).
+//
+// ALIGNED: N % 8 == 0 and the sample rows are 8-byte aligned, so that whole
+// chunks can take the fast loads.
 template <int FORM, bool ALIGNED>
 __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, int32_t* vis,
                                           int N, long long row_stride, long long NB, int f,
                                           int I, int J, int t_begin, int t_end, int mode,
                                           uint8_t* lds) {
-  const bool diag = (I == J);
-  const int nchunks = t_end > t_begin ? (t_end - t_begin + KC - 1) / KC : 0;
+  const int len = t_end > t_begin ? t_end - t_begin : 0;
+  const int nchunks = (len + KC - 1) / KC;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1, half = lane >> 5;
 
-  // MFMA blocks of this wave that hold baselines of the triangle
+  // MFMA blocks of this wave that hold baselines of the triangle; a wave with
+  // none (below the diagonal, or past N) skips the MFMAs, the others compute
+  // all four blocks and drop the surplus at the write.
   const int rs0 = I * BT + 64 * wr, cs0 = J * BT + 64 * wc;
   int mask = 0;
 #pragma unroll
@@ -222,46 +280,87 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     const int rs = rs0 + 32 * (ab >> 1), cs = cs0 + 32 * (ab & 1);
     if (rs < N && cs < N && cs >= rs) mask |= 1 << ab;
   }
+  int offA[2], offB[2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    const int seg0 = (FORM == FORM_I8) ? half : 2 * half;
+    offA[x] = seg_off(64 * wr + 32 * x + (lane & 31), seg0);
+    offB[x] = BLOCK_LDS + seg_off(64 * wc + 32 * x + (lane & 31), seg0);
+  }
 
-  // staging role: threads 0..127 load the I block, 128..255 the J block
-  const int sblk = tid >> 7, h = tid & 127, ng = h & 15, tg = h >> 4;
-  const bool sactive = (sblk == 0) || !diag;
+  // staging role: threads 0..127 load the I block, 128..255 the J block; in
+  // a 128-thread half, thread h covers inputs 8*(h >> 3).. and times 8*(h & 7)..
+  const int sblk = tid >> 7, h = tid & 127, tg = h & 7, ng = h >> 3;
+  const bool sactive = true;  // diagonal tiles: the J threads stage a copy of the I block
   const int n0 = (sblk ? J : I) * BT + 8 * ng;
+  const bool inside_n = ALIGNED && n0 < N;  // N % 8 == 0: the 8 inputs are all present
+  // uniform row pointer of this channel at t_begin, and the lane's offset
+  const uint8_t* rows = samples + (long long)t_begin * row_stride + (long long)f * N;
+  const uint32_t lane_off = (uint32_t)(8 * tg) * (uint32_t)row_stride + (uint32_t)n0;
 
   typedef typename Acc<FORM>::T V;
-  V re[2][2], im[2][2];
+  TileCtx<FORM> x;
+  x.lds = lds;
+  x.rows = rows;
+  x.row_stride = row_stride;
+  // edge tiles (N % 8 == 0): inputs past N load a valid row instead; their LDS
+  // rows only reach baselines past N, which are never written
+  x.lane_off = (uint32_t)(8 * tg) * (uint32_t)row_stride + (uint32_t)(inside_n ? n0 : 0);
+  x.sblk = sblk;
+  x.ng = ng;
+  x.tg = tg;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int y = 0; y < 2; ++y) {
+    x.offA[y] = offA[y];
+    x.offB[y] = offB[y];
+  }
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      re[x][y] = V{};
-      im[x][y] = V{};
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      x.re[p][q] = V{};
+      x.im[p][q] = V{};
     }
 
-  uint2 raw[8];
-  if (nchunks > 0) {
-    load_chunk<ALIGNED>(raw, samples, row_stride, f, N, n0, t_begin + 8 * tg, t_end, sactive);
-    if (sactive) stage_chunk<FORM>(raw, lds + sblk * BLOCK_LDS, 8 * ng, tg);
+  // Steady state over the chunks whose loads all lie inside the frame (the
+  // diagonal tile's J threads stage a second copy of the I block, which keeps
+  // the loop free of branches).
+  const int nfast = ALIGNED ? len / KC : 0;
+  const int nsteady = nfast & ~1;
+  int c = 0;
+  if (nsteady >= 2) {
+    if (mask)
+      steady_chunks<FORM, true>(x, nsteady, nfast);
+    else
+      steady_chunks<FORM, false>(x, nsteady, nfast);
+    c = nsteady;
   }
-  __syncthreads();
 
-  for (int c = 0; c < nchunks; ++c) {
+  // General loop: the remaining chunks (frame edges, ragged tail, short
+  // ranges), one buffer flip per chunk.
+  uint2 raw[8];
+  auto load = [&](int cc) {
+    if (inside_n && (cc + 1) * KC <= len)
+      load_block_fast(raw, rows + (long long)cc * KC * row_stride, row_stride, lane_off);
+    else
+      load_block_edge(raw, samples, row_stride, f, N, n0, t_begin + cc * KC + 8 * tg, t_end,
+                      sactive);
+  };
+  if (c < nchunks) {
+    load(c);
+    if (sactive) stage_chunk<FORM>(raw, lds + (c & 1) * STAGE_LDS + sblk * BLOCK_LDS, 8 * ng, tg);
+    __syncthreads();
+  }
+  for (; c < nchunks; ++c) {
     uint8_t* cur = lds + (c & 1) * STAGE_LDS;
     uint8_t* nxt = lds + ((c + 1) & 1) * STAGE_LDS;
     const bool more = c + 1 < nchunks;
-    if (more)
-      load_chunk<ALIGNED>(raw, samples, row_stride, f, N, n0, t_begin + (c + 1) * KC + 8 * tg,
-                          t_end, sactive);
-    if (mask) {
-      const uint8_t* ldsI = cur;
-      const uint8_t* ldsJ = diag ? cur : cur + BLOCK_LDS;
-      compute_chunk<FORM>(ldsI, ldsJ, 64 * wr + (lane & 31), 64 * wc + (lane & 31), half, mask,
-                          re, im);
-    }
+    if (more) load(c + 1);
+    if (mask) compute_chunk<FORM>(cur, offA, offB, x.re, x.im);
     if (more && sactive) stage_chunk<FORM>(raw, nxt + sblk * BLOCK_LDS, 8 * ng, tg);
     __syncthreads();
   }
-  if (mask) write_blocks(vis, N, NB, f, rs0, cs0, lane, mask, mode, re, im);
+  if (mask) write_blocks(vis, N, NB, f, rs0, cs0, lane, mask, mode, x.re, x.im);
 }
 
 template <int FORM, bool ALIGNED>

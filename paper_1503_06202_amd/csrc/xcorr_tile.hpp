@@ -16,12 +16,13 @@
 //
 // Operand staging.  Global memory holds samples[t][f][n] (n fastest), while an
 // MFMA lane needs consecutive samples of one input.  Each workgroup therefore
-// loads a chunk of KC = 64 samples x 128 inputs with coalesced 8-byte loads,
-// transposes 8x8 byte blocks in registers (v_perm), splits the nibbles,
-// removes the +8 offset and stores 16-byte segments [r(8 samples), m(8
-// samples)] into LDS.  A row of LDS holds the 8 segments of one input; the
-// segment position is XOR-swizzled with the row so that both the staging
-// writes and the MFMA operand reads are free of bank conflicts.
+// loads a chunk of KC = 64 samples x 128 inputs with 8-byte loads, transposes
+// 8x8 byte blocks in registers (v_perm), splits the nibbles, removes the +8
+// offset and stores 16-byte segments [r(8 samples), m(8 samples)] into LDS.
+// A row of LDS holds the 8 segments of one input, padded to 144 bytes: eight
+// lanes reading eight consecutive rows at one segment then hit disjoint banks,
+// and the staging lanes, which write the 8 segments of a row side by side,
+// too.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,7 +37,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int BT = 128;        // tile edge (inputs)
 constexpr int KC = 64;         // samples per staged chunk
-constexpr int ROWB = 2 * KC;   // bytes per LDS row (r and m of KC samples)
+constexpr int ROWB = 2 * KC + 16;  // bytes per LDS row (r and m of KC samples, padded)
 constexpr int NTHREADS = 256;  // 4 waves: 2 x 2 wave tiles of 64 x 64
 constexpr int BLOCK_LDS = BT * ROWB;          // one operand block, bytes
 constexpr int STAGE_LDS = 2 * BLOCK_LDS;      // I block + J block
@@ -45,9 +46,7 @@ constexpr int LDS_BYTES = 2 * STAGE_LDS;      // double buffered
 enum Form { FORM_I8 = 0, FORM_F8 = 1 };
 
 // Byte offset of 16-byte segment q (0..7) of LDS row r.
-__device__ __forceinline__ int seg_off(int r, int q) {
-  return r * ROWB + 16 * (q ^ (r & 7) ^ ((r >> 3) & 7));
-}
+__device__ __forceinline__ int seg_off(int r, int q) { return r * ROWB + 16 * q; }
 
 // Transpose a 4x4 byte block: d[k] holds bytes (n0..n3) of time k; on return
 // d[n] holds bytes (t0..t3) of input n.
