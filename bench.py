@@ -45,7 +45,110 @@ def parse():
                          "count for scaling the HBM counters of a profiler run)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
+    ap.add_argument("--forms", default="f8,batched,stream",
+                    help="other forms reported beside the headline line (comma list of f8, "
+                         "batched, stream; empty for none)")
+    ap.add_argument("--stream-frames", type=int, default=1000)
     return ap.parse_args()
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _time_calls(fn, steps, torch):
+    """Mean ms of `steps` calls of fn, bracketed by device synchronisation."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_fp8(d, w, steps, torch):
+    """The FP8 e4m3 form on the same frame (f32 sums flushed to int32)."""
+    from paper_1503_06202_amd import Plan, vis_shape
+
+    vis = torch.empty(vis_shape(w.N, w.F), dtype=torch.int32, device=d.device)
+    with Plan(w.N, w.F, w.T, form="f8") as p:
+        ms = _time_calls(lambda: p.correlate(d, vis), steps, torch)
+    ops = 8.0 * w.cmac / (ms / 1e3) / 1e12
+    return {"workload": w.name, "ms_per_frame": ms, "cmac_per_s": w.cmac / (ms / 1e3),
+            "tflops": ops, "pct_fp8_peak": 100.0 * ops / PEAK_TOPS["f8"]}
+
+
+def bench_batched(steps, torch):
+    """48 uneven instances (N in 64..2048, T in 8192..32768, F = 4) in one graph-replayed
+    persistent launch, against the plain int8 form called instance by instance."""
+    import synth
+    from paper_1503_06202_amd import BatchPlan, Plan, tune, vis_shape
+
+    insts = synth.batch_instances()
+    t0 = time.perf_counter()
+    frames = [torch.from_numpy(synth.batch_frame(i, inst)).cuda() for i, inst in enumerate(insts)]
+    _log(f"bench: batched: {len(insts)} instances generated in {time.perf_counter() - t0:.1f} s")
+    vis = [torch.empty(vis_shape(N, F), dtype=torch.int32, device=frames[0].device)
+           for N, F, T in insts]
+    t0 = time.perf_counter()
+    splits = tune.tune(insts, frames=frames, cache_path=None)
+    tune_s = time.perf_counter() - t0
+    cmac = sum(F * T * N * (N + 1) // 2 for N, F, T in insts)
+    with BatchPlan(insts, split_t=splits) as bp:
+        batched_ms = _time_calls(lambda: bp.correlate(frames, vis, graph=True), steps, torch)
+        ref = [v.clone() for v in vis]
+    plans = [Plan(N, F, T) for N, F, T in insts]
+
+    def plain():
+        for p, fr, v in zip(plans, frames, vis):
+            p.correlate(fr, v)
+
+    plain_ms = _time_calls(plain, steps, torch)
+    same = all(torch.equal(a, b) for a, b in zip(ref, vis))
+    for p in plans:
+        p.close()
+    return {"instances": len(insts), "cmac_per_launch": cmac, "tune_s": tune_s,
+            "split_t": splits, "batched_graph_ms": batched_ms,
+            "batched_cmac_per_s": cmac / (batched_ms / 1e3),
+            "plain_int8_ms": plain_ms, "plain_int8_cmac_per_s": cmac / (plain_ms / 1e3),
+            "batched_over_plain": plain_ms / batched_ms, "batched_equals_plain": bool(same)}
+
+
+def bench_stream(n_frames, torch):
+    """Request loop: frames (N=2048, F=4, T=32768) at Poisson arrivals, continuous
+    batching over 8 slots, device-resident accumulator dumped every 256 frames."""
+    import synth
+    from paper_1503_06202_amd.stream import Frame, GpuLauncher, RequestLoop, poisson_arrivals
+
+    w = synth.workload("stream_frame")
+    pool = [torch.from_numpy(synth.stream_frame(k)).cuda() for k in range(8)]
+    launcher = GpuLauncher(w.N, w.F, w.T, slots=8, streams=1, graph=True)
+    out = {"frame": {"N": w.N, "F": w.F, "T": w.T}, "slots": 8, "distinct_frames": len(pool),
+           "cmac_per_frame": w.cmac}
+
+    def run(n, rate, seed):
+        arr = poisson_arrivals(n, rate, seed)
+        frames = [Frame(k, 0, pool[k % len(pool)], float(arr[k])) for k in range(n)]
+        loop = RequestLoop(launcher, max_inflight=2, dump_every=256)
+        rep = loop.run(frames)
+        torch.cuda.synchronize()
+        return rep
+
+    sat = run(200, float("inf"), 1)
+    mu = sat.frames_per_s
+    out["saturated"] = sat.summary()
+    out["service_rate_frames_per_s"] = mu
+    out["saturated_cmac_per_s"] = mu * w.cmac
+    for rho in (0.5, 0.9):
+        rep = run(n_frames, rho * mu, 2)
+        out[f"poisson_rho_{rho}"] = rep.summary()
+    frame_period = w.T * SAMPLE_PERIOD_S   # the sample clock: one frame every 83.9 ms
+    rep = run(24, 1.0 / frame_period, 3)
+    out["realtime_cadence"] = rep.summary()
+    out["realtime_frame_period_ms"] = frame_period * 1e3
+    launcher.close()
+    return out
 
 
 def cpu_baseline(frame, w):
@@ -157,9 +260,23 @@ def main():
         torch.cuda.synchronize()
         out["calibration_copy_bytes"] = 2 * d.numel()
         del dst
+    plan.close()
+    forms = [f for f in args.forms.split(",") if f]
+    extra = {}
+    if "f8" in forms:
+        _log("bench: fp8 form")
+        extra["fp8"] = bench_fp8(d, w, args.steps, torch)
+    if "batched" in forms:
+        _log("bench: batched form")
+        extra["batched"] = bench_batched(max(3, args.steps // 4), torch)
+    if "stream" in forms:
+        _log("bench: streaming loop")
+        extra["stream"] = bench_stream(args.stream_frames, torch)
+        out["p99_frame_latency_ms"] = extra["stream"]["poisson_rho_0.9"]["p99_ms"]
+    if extra:
+        out["forms"] = extra
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frame, w)
-    plan.close()
     print(json.dumps(out), flush=True)
 
 

@@ -65,7 +65,9 @@ enum {
     XENG_FORM_I8 = 0,        /* int8 MFMA, int32 accumulators (default) */
     XENG_FORM_F8 = 1,        /* FP8 e4m3 MFMA, f32 accumulators flushed to int32 */
     XENG_FORM_MASK = 0xff,
-    XENG_ACCUMULATE = 1 << 8 /* add into vis instead of overwriting it */
+    XENG_ACCUMULATE = 1 << 8, /* add into vis instead of overwriting it */
+    XENG_SHARED_VIS = 1 << 9  /* batch plans only, with XENG_ACCUMULATE: instances may share
+                                 a vis buffer; every write is an int32 atomic add (exact) */
 };
 
 #define XENG_T_EXACT_MAX 16777215 /* 2^24 - 1 */
@@ -129,21 +131,26 @@ typedef struct xeng_instance {
 
 /*
  * Plan a batch of `count` instances (copied; descs may be freed after the
- * call).  flags as for xeng_plan (the form applies to every instance).
- * The plan owns a device table of work items, built on first use.
+ * call).  flags as for xeng_plan (the form applies to every instance), plus
+ * XENG_SHARED_VIS, which needs XENG_ACCUMULATE.  The plan owns a device table
+ * of work items, built on first use.
  * Errors: XENG_EINVAL (out or descs NULL, count < 1, any N, F or T < 1,
- * any N > XENG_N_MAX, negative split_t, unknown flags), XENG_EOVERFLOW (any T > XENG_T_EXACT_MAX),
- * XENG_ENOMEM.
+ * any N > XENG_N_MAX, negative split_t, unknown flags, XENG_SHARED_VIS without
+ * XENG_ACCUMULATE), XENG_EOVERFLOW (any T > XENG_T_EXACT_MAX), XENG_ENOMEM.
  */
 int xeng_plan_batch(xeng_plan_t *out, const xeng_instance *descs, int count, unsigned flags);
 
 /*
  * Correlate every instance of a batch plan: samples[k] and vis[k] are the
  * device buffers of instance k (host arrays of count device pointers).  One
- * persistent kernel launch covers all instances.  Pointers are copied to the
- * device through plan-owned pinned staging on the given stream.
- * Errors: XENG_EINVAL (NULL plan or arrays, NULL element), XENG_EPLAN (not a
- * batch plan), XENG_EHIP, XENG_ENOMEM.
+ * persistent kernel launch covers all instances.  An instance whose samples[k]
+ * is NULL is skipped by this call (its vis[k] is ignored and untouched), so a
+ * plan over a pool of slots serves any subset of them.  Pointers are copied to
+ * the device through plan-owned pinned staging on the given stream; the call
+ * waits on the host only when the pointers changed while the previous copy is
+ * still pending.
+ * Errors: XENG_EINVAL (NULL plan or arrays, NULL vis[k] of an active
+ * instance), XENG_EPLAN (not a batch plan), XENG_EHIP, XENG_ENOMEM.
  */
 int xeng_correlate_batch(xeng_plan_t p, const uint8_t *const *samples, int32_t *const *vis,
                          void *stream);

@@ -20,6 +20,7 @@ XENG_ENOMEM = -5
 XENG_FORM_I8 = 0
 XENG_FORM_F8 = 1
 XENG_ACCUMULATE = 1 << 8
+XENG_SHARED_VIS = 1 << 9
 
 XENG_T_EXACT_MAX = (1 << 24) - 1
 XENG_N_MAX = 32768

@@ -397,6 +397,7 @@ __global__ void __launch_bounds__(NTHREADS, 2)
     if (k >= nitems) break;
     const BatchItem it = items[k];
     const BatchInst in = insts[it.inst];
+    if (!in.samples) continue;  // instance not active in this call (uniform branch)
     const long long NB = (long long)in.N * (in.N + 1) / 2;
     const long long stride = (long long)in.F * in.N;
     if (in.aligned)

@@ -61,10 +61,15 @@ int hip_fail(xeng_plan_t p, hipError_t e, const char* what) {
   return XENG_EHIP;
 }
 
-bool flags_ok(unsigned flags) {
+bool flags_ok(unsigned flags, bool batch = false) {
   const unsigned form = flags & XENG_FORM_MASK;
   if (form != XENG_FORM_I8 && form != XENG_FORM_F8) return false;
-  return (flags & ~(unsigned)(XENG_FORM_MASK | XENG_ACCUMULATE)) == 0;
+  unsigned known = XENG_FORM_MASK | XENG_ACCUMULATE;
+  if (batch) {
+    known |= XENG_SHARED_VIS;
+    if ((flags & XENG_SHARED_VIS) && !(flags & XENG_ACCUMULATE)) return false;
+  }
+  return (flags & ~known) == 0;
 }
 
 int ensure_cu_count(xeng_plan_t p) {
@@ -194,7 +199,7 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
 int xeng_plan_batch(xeng_plan_t* out, const xeng_instance* descs, int count, unsigned flags) {
   if (!out) return XENG_EINVAL;
   *out = nullptr;
-  if (!descs || count < 1 || !flags_ok(flags)) return XENG_EINVAL;
+  if (!descs || count < 1 || !flags_ok(flags, true)) return XENG_EINVAL;
   for (int k = 0; k < count; ++k) {
     const xeng_instance& d = descs[k];
     if (d.N < 1 || d.F < 1 || d.T < 1 || d.N > XENG_N_MAX || d.split_t < 0) return XENG_EINVAL;
@@ -207,6 +212,7 @@ int xeng_plan_batch(xeng_plan_t* out, const xeng_instance* descs, int count, uns
   p->flags = flags;
   p->form = (int)(flags & XENG_FORM_MASK);
   p->accumulate = (flags & XENG_ACCUMULATE) != 0;
+  const bool shared = (flags & XENG_SHARED_VIS) != 0;
   try {
     p->insts.assign(descs, descs + count);
     p->inst_zero.assign(count, 0);
@@ -226,7 +232,8 @@ int xeng_plan_batch(xeng_plan_t* out, const xeng_instance* descs, int count, uns
       int len = (d.T + S - 1) / S;
       len = (len + kChunk - 1) / kChunk * kChunk;
       S = (d.T + len - 1) / len;
-      const int mode = S > 1 ? xeng::WM_ATOMIC : (p->accumulate ? xeng::WM_ADD : xeng::WM_STORE);
+      const int mode = (S > 1 || shared) ? xeng::WM_ATOMIC
+                                         : (p->accumulate ? xeng::WM_ADD : xeng::WM_STORE);
       if (S > 1 && !p->accumulate) {
         p->inst_zero[k] = 1;
         p->any_zero = true;
@@ -292,7 +299,8 @@ static int batch_upload(xeng_plan_t p, const uint8_t* const* samples, int32_t* c
   const size_t ni = p->insts.size();
   bool same = p->uploaded.size() == 2 * ni;
   for (size_t k = 0; same && k < ni; ++k)
-    same = p->uploaded[2 * k] == samples[k] && p->uploaded[2 * k + 1] == vis[k];
+    same = p->uploaded[2 * k] == samples[k] &&
+           p->uploaded[2 * k + 1] == (samples[k] ? vis[k] : nullptr);
   if (same) return XENG_OK;
   if (p->copy_pending) {
     // the pinned staging may still be read by the previous call's copy
@@ -305,15 +313,15 @@ static int batch_upload(xeng_plan_t p, const uint8_t* const* samples, int32_t* c
     const xeng_instance& d = p->insts[k];
     xeng::BatchInst& b = p->h_insts[k];
     b.samples = samples[k];
-    b.vis = vis[k];
+    b.vis = samples[k] ? vis[k] : nullptr;
     b.N = d.N;
     b.F = d.F;
     b.T = d.T;
     b.aligned = (d.N % 8 == 0) && ((reinterpret_cast<uintptr_t>(samples[k]) & 7) == 0);
-    b.zero = p->inst_zero[k];
+    b.zero = samples[k] ? p->inst_zero[k] : 0;
     b.pad = 0;
     p->uploaded[2 * k] = samples[k];
-    p->uploaded[2 * k + 1] = vis[k];
+    p->uploaded[2 * k + 1] = b.vis;
   }
   hipError_t e = hipMemcpyAsync(p->d_insts, p->h_insts, ni * sizeof(xeng::BatchInst),
                                 hipMemcpyHostToDevice, s);
@@ -330,7 +338,7 @@ static int batch_check(xeng_plan_t p, const uint8_t* const* samples, int32_t* co
   if (!p || !samples || !vis) return XENG_EINVAL;
   if (p->kind != PLAN_BATCH) return XENG_EPLAN;
   for (size_t k = 0; k < p->insts.size(); ++k)
-    if (!samples[k] || !vis[k]) return XENG_EINVAL;
+    if (samples[k] && !vis[k]) return XENG_EINVAL;
   return XENG_OK;
 }
 

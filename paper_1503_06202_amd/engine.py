@@ -130,7 +130,8 @@ class BatchPlan:
     """Many independent (N, F, T) instances correlated by one persistent launch."""
 
     def __init__(self, instances: Sequence[Tuple[int, int, int]], form: str = "i8",
-                 accumulate: bool = False, split_t: Optional[Sequence[int]] = None):
+                 accumulate: bool = False, split_t: Optional[Sequence[int]] = None,
+                 shared_vis: bool = False):
         if form not in FORMS:
             raise ValueError(f"form must be one of {sorted(FORMS)}")
         self.instances: List[Tuple[int, int, int]] = [tuple(map(int, x)) for x in instances]
@@ -143,26 +144,41 @@ class BatchPlan:
         for k, ((N, F, T), s) in enumerate(zip(self.instances, splits)):
             arr[k] = _lib.XengInstance(N, F, T, int(s))
         flags = FORMS[form] | (_lib.XENG_ACCUMULATE if accumulate else 0)
+        if shared_vis:
+            flags |= _lib.XENG_SHARED_VIS
         h = ctypes.c_void_p()
         _lib.check(_lib.lib().xeng_plan_batch(ctypes.byref(h), arr, n, flags), "xeng_plan_batch")
         self._h = h
         self._keep = None
 
-    def _arrays(self, samples: Sequence[torch.Tensor], vis: Sequence[torch.Tensor]):
+    def _arrays(self, samples: Sequence[Optional[torch.Tensor]],
+                vis: Sequence[Optional[torch.Tensor]]):
+        """Pointer arrays; a None sample tensor skips that instance this call."""
         n = len(self.instances)
         if len(samples) != n or len(vis) != n:
-            raise ValueError(f"need {n} sample and vis tensors")
+            raise ValueError(f"need {n} sample and vis entries")
+        sp = (ctypes.c_void_p * n)()
+        vp = (ctypes.c_void_p * n)()
         for k, (N, F, T) in enumerate(self.instances):
+            if samples[k] is None:
+                continue
             Ts, Fs, Ns = _check_samples(samples[k])
             if (Ts, Fs, Ns) != (T, F, N):
                 raise ValueError(f"instance {k}: samples shape {(Ts, Fs, Ns)} != planned {(T, F, N)}")
+            if vis[k] is None:
+                raise ValueError(f"instance {k} is active and needs its vis")
             _check_vis(vis[k], N, F, samples[k].device)
-        sp = (ctypes.c_void_p * n)(*[s.data_ptr() for s in samples])
-        vp = (ctypes.c_void_p * n)(*[v.data_ptr() for v in vis])
+            sp[k] = samples[k].data_ptr()
+            vp[k] = vis[k].data_ptr()
         return sp, vp
 
-    def correlate(self, samples: Sequence[torch.Tensor], vis: Sequence[torch.Tensor],
+    def correlate(self, samples: Sequence[Optional[torch.Tensor]],
+                  vis: Sequence[Optional[torch.Tensor]],
                   stream: Optional[torch.cuda.Stream] = None, graph: bool = False) -> None:
+        """Correlate the active instances (samples[k] not None) in one launch.
+
+        With ``graph`` the launch replays a HIP graph captured on first use.
+        """
         sp, vp = self._arrays(samples, vis)
         fn = _lib.lib().xeng_correlate_batch_graph if graph else _lib.lib().xeng_correlate_batch
         rc = fn(self._h, sp, vp, _stream_handle(stream))

@@ -91,16 +91,27 @@ def test_batch_validation_needs_no_gpu(L):
     assert plan([(8, 1, 1, -1)])[0] == _lib.XENG_EINVAL
     assert plan([(8, 1, 1 << 24, 0)])[0] == _lib.XENG_EOVERFLOW
     assert plan([(8, 1, 8, 0)], flags=7)[0] == _lib.XENG_EINVAL
+    # shared outputs are atomic adds: only meaningful when accumulating
+    assert plan([(8, 1, 8, 0)], flags=_lib.XENG_SHARED_VIS)[0] == _lib.XENG_EINVAL
+    rc, hs = plan([(8, 1, 8, 0)], flags=_lib.XENG_SHARED_VIS | _lib.XENG_ACCUMULATE)
+    assert rc == 0
+    L.xeng_destroy(hs)
+    # and single plans do not take the flag
+    h1 = ctypes.c_void_p()
+    assert L.xeng_plan(ctypes.byref(h1), 8, 1, 8, _lib.XENG_SHARED_VIS | _lib.XENG_ACCUMULATE) == _lib.XENG_EINVAL
     h = ctypes.c_void_p()
     assert L.xeng_plan_batch(ctypes.byref(h), None, 1, 0) == _lib.XENG_EINVAL
     rc, hb = plan([(64, 4, 8192, 0), (33, 1, 100, 3)])
     assert rc == 0 and hb.value
     dummy = ctypes.c_void_p(0x1000)
     try:
-        arr = (ctypes.c_void_p * 2)(dummy, None)
-        assert L.xeng_correlate_batch(hb, arr, arr, None) == _lib.XENG_EINVAL
-        assert L.xeng_correlate_batch(hb, None, arr, None) == _lib.XENG_EINVAL
-        assert L.xeng_correlate_batch_graph(hb, arr, arr, None) == _lib.XENG_EINVAL
+        both = (ctypes.c_void_p * 2)(dummy, dummy)
+        half = (ctypes.c_void_p * 2)(dummy, None)
+        # an active instance (non-NULL samples) needs its vis
+        assert L.xeng_correlate_batch(hb, both, half, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate_batch(hb, None, both, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate_batch(hb, both, None, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate_batch_graph(hb, both, half, None) == _lib.XENG_EINVAL
         # a single plan is not a batch plan, and the other way round
         rc, hs = _plan(L, 8, 1, 8)
         ok = (ctypes.c_void_p * 2)(dummy, dummy)

@@ -1,0 +1,68 @@
+"""The streaming loop and the autotuner on the GPU (parity with the oracle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1503_06202_amd import BatchPlan, Plan, tune, vis_shape
+from paper_1503_06202_amd.stream import Frame, GpuLauncher, RequestLoop, poisson_arrivals
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_request_loop_accumulates_exactly(graph):
+    N, F, T, streams = 136, 2, 320, 3
+    rng = np.random.default_rng(17)
+    host = [rng.integers(0, 256, (T, F, N), dtype=np.uint8) for _ in range(12)]
+    pool = [torch.from_numpy(h).cuda() for h in host]
+    n = 40
+    arr = poisson_arrivals(n, 4000.0, 5)
+    frames = [Frame(k, k % streams, pool[k % len(pool)], float(arr[k])) for k in range(n)]
+    la = GpuLauncher(N, F, T, slots=4, streams=streams, graph=graph)
+    rep = RequestLoop(la, max_inflight=2, dump_every=5).run(frames)
+    torch.cuda.synchronize()
+    assert rep.frames == n and max(rep.batch_sizes) <= 4
+    for st in range(streams):
+        want = sum(oracle.correlate(host[k % len(host)]) for k in range(n) if k % streams == st)
+        dumped = [d for s, c, d in rep.dumps if s == st]
+        got = sum(h.numpy().astype(np.int64) for (_, h, _) in dumped) + la.acc[st].cpu().numpy()
+        assert np.array_equal(got, want), st
+    la.close()
+
+
+def test_alone_equals_share_in_mix():
+    # each frame alone (plain plan) equals what it adds to its stream's accumulator
+    N, F, T = 200, 1, 256
+    rng = np.random.default_rng(3)
+    fr = [torch.from_numpy(rng.integers(0, 256, (T, F, N), dtype=np.uint8)).cuda() for _ in range(5)]
+    with Plan(N, F, T) as p:
+        alone = [p.correlate(x).clone() for x in fr]
+    acc = torch.zeros(vis_shape(N, F), dtype=torch.int32, device="cuda")
+    with BatchPlan([(N, F, T)] * 5, accumulate=True, shared_vis=True) as bp:
+        bp.correlate(fr, [acc] * 5)
+        torch.cuda.synchronize()
+        assert torch.equal(acc, sum(alone))
+        # a subset of slots: the others are skipped and add nothing
+        acc2 = torch.zeros_like(acc)
+        bp.correlate([fr[0], None, fr[2], None, None], [acc2, None, acc2, None, None], graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(acc2, alone[0] + alone[2])
+
+
+def test_tuner_choices_are_exact(tmp_path):
+    insts = [(64, 2, 1024)] * 3 + [(130, 1, 512), (256, 2, 2048)]
+    path = str(tmp_path / "tune.json")
+    splits = tune.tune(insts, cache_path=path, reps=2)
+    assert len(splits) == len(insts) and all(s in tune.CANDIDATES for s in splits)
+    # the cache is reused
+    assert tune.tune(insts, cache_path=path, reps=2) == splits
+    rng = np.random.default_rng(8)
+    host = [rng.integers(0, 256, (T, F, N), dtype=np.uint8) for N, F, T in insts]
+    d = [torch.from_numpy(h).cuda() for h in host]
+    vis = [torch.empty(vis_shape(N, F), dtype=torch.int32, device="cuda") for N, F, T in insts]
+    with BatchPlan(insts, split_t=splits) as bp:
+        bp.correlate(d, vis, graph=True)
+        torch.cuda.synchronize()
+    for h, v in zip(host, vis):
+        assert np.array_equal(v.cpu().numpy(), oracle.to_int32(oracle.correlate(h)))

@@ -1,0 +1,120 @@
+"""The streaming request loop's admission, batching and dump logic, on the CPU
+with a fake launcher that completes launches after a fixed service time on a
+virtual clock and integrates frames with the oracle."""
+import collections
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_06202_amd.stream import Frame, RequestLoop, poisson_arrivals
+
+
+class VClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += dt
+
+
+class FakeLauncher:
+    def __init__(self, clock, slots, service_s, per_frame_s=0.0, streams=1):
+        self.clock, self.slots = clock, slots
+        self.service_s, self.per_frame_s = service_s, per_frame_s
+        self.acc = collections.defaultdict(lambda: 0)
+        self.in_device = 0
+        self.max_in_device = 0
+        self.launches = []
+
+    def launch(self, frames):
+        done_at = self.clock() + self.service_s + self.per_frame_s * len(frames)
+        if self.launches and self.launches[-1] > self.clock():
+            done_at = self.launches[-1] + self.service_s + self.per_frame_s * len(frames)
+        self.launches.append(done_at)
+        for f in frames:
+            self.acc[f.stream] = self.acc[f.stream] + oracle.correlate(f.samples)
+        self.in_device += len(frames)
+        self.max_in_device = max(self.max_in_device, self.in_device)
+        return (done_at, len(frames))
+
+    def ready(self, token):
+        ok = self.clock() >= token[0]
+        if ok:
+            self.in_device -= token[1]
+            token_done = True  # noqa: F841
+        return ok
+
+    def poll_wait(self, token):
+        self.clock.t = max(self.clock.t, token[0])
+
+    def dump(self, stream):
+        out = self.acc[stream]
+        self.acc[stream] = 0
+        return out
+
+
+def frames_for(n, streams, rate, seed=0, N=6, F=2, T=16):
+    rng = np.random.default_rng(seed)
+    arr = poisson_arrivals(n, rate, seed)
+    return [Frame(k, k % streams, rng.integers(0, 256, (T, F, N), dtype=np.uint8), float(arr[k]))
+            for k in range(n)]
+
+
+def test_every_frame_completes_with_latency_at_least_service():
+    clk = VClock()
+    la = FakeLauncher(clk, slots=4, service_s=0.002)
+    fr = frames_for(60, 1, rate=300.0)
+    rep = RequestLoop(la, max_inflight=2, dump_every=1000, clock=clk, sleep=clk.sleep).run(fr)
+    assert rep.frames == 60
+    assert (rep.latencies_ms >= 2.0 - 1e-9).all()
+    assert la.max_in_device <= 4
+
+
+def test_overload_batches_and_respects_slots():
+    # all frames at t = 0: the loop must batch up to `slots` and never exceed it
+    clk = VClock()
+    la = FakeLauncher(clk, slots=5, service_s=0.001)
+    fr = frames_for(40, 2, rate=float("inf"))
+    rep = RequestLoop(la, max_inflight=2, dump_every=1000, clock=clk, sleep=clk.sleep).run(fr)
+    assert rep.frames == 40
+    assert max(rep.batch_sizes) <= 5 and sum(rep.batch_sizes) == 40
+    assert max(rep.batch_sizes) > 1
+    assert la.max_in_device <= 5
+
+
+def test_continuous_batching_picks_up_arrivals_during_flight():
+    # slow service, frequent arrivals: later launches carry several frames
+    clk = VClock()
+    la = FakeLauncher(clk, slots=8, service_s=0.010)
+    fr = frames_for(50, 1, rate=1000.0)
+    rep = RequestLoop(la, max_inflight=1, dump_every=1000, clock=clk, sleep=clk.sleep).run(fr)
+    assert rep.frames == 50
+    assert np.mean(rep.batch_sizes[1:]) > 3
+
+
+@pytest.mark.parametrize("streams,dump_every", [(1, 7), (3, 5)])
+def test_dumps_plus_pending_equal_sum_of_frames(streams, dump_every):
+    clk = VClock()
+    la = FakeLauncher(clk, slots=3, service_s=0.001, streams=streams)
+    fr = frames_for(45, streams, rate=2000.0, seed=3)
+    rep = RequestLoop(la, max_inflight=2, dump_every=dump_every, clock=clk, sleep=clk.sleep).run(fr)
+    for st in range(streams):
+        want = sum(oracle.correlate(f.samples) for f in fr if f.stream == st)
+        dumped = [d for s, n, d in rep.dumps if s == st]
+        counts = [n for s, n, d in rep.dumps if s == st]
+        assert all(n >= dump_every for n in counts)
+        total = sum(dumped) + la.acc[st]
+        assert np.array_equal(total, want)
+        assert sum(counts) + rep.pending.get(st, 0) == sum(1 for f in fr if f.stream == st)
+
+
+def test_rejects_bad_configuration():
+    clk = VClock()
+    with pytest.raises(ValueError):
+        RequestLoop(FakeLauncher(clk, slots=0, service_s=0.001))
+    with pytest.raises(ValueError):
+        RequestLoop(FakeLauncher(clk, slots=1, service_s=0.001), max_inflight=0)
