@@ -11,64 +11,66 @@
 
 namespace xeng {
 
-// Inputs of one staging thread: an 8 x 8 byte block, inputs n0..n0+7 at times
-// t0..t0+7 of one channel; raw[k] holds time t0 + k (x: n0..n0+3, y: n0+4..n0+7).
-//
-// Fast path: the whole block lies inside the frame and rows are 8-byte aligned.
-// The row pointer is uniform across the workgroup plus a per-lane 32-bit
-// offset, so the loads need no per-load vector address arithmetic.
-__device__ __forceinline__ void load_block_fast(uint2 (&raw)[8], const uint8_t* __restrict__ rows,
-                                                long long row_stride, uint32_t lane_off) {
+// Staging role of a thread within its block's 128 threads: it covers the 16
+// inputs 16*seg.. of the block at the four times r0, r0+16, r0+32, r0+48 of a
+// chunk, with r0 = 8*((h >> 3) & 1) + (h >> 4).  Eight consecutive lanes read
+// one 128-byte row; sixteen consecutive lanes write two plane rows 8 apart.
+struct StageRole {
+  int seg, r0;
+  __device__ __forceinline__ explicit StageRole(int h) : seg(h & 7), r0(8 * ((h >> 3) & 1) + (h >> 4)) {}
+};
+
+// Fast path: the four pieces lie inside the frame.  `rows` points at the
+// chunk's first row of this channel (uniform across the workgroup); lane_off
+// adds the thread's row r0 and its inputs.
+__device__ __forceinline__ void load_pieces_fast(v4i (&raw)[4], const uint8_t* __restrict__ rows,
+                                                 long long row_stride, uint32_t lane_off) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k)
-    raw[k] = *reinterpret_cast<const uint2*>(rows + k * row_stride + lane_off);
+  for (int k = 0; k < 4; ++k)
+    raw[k] = *reinterpret_cast<const v4i*>(rows + (long long)(16 * k) * row_stride + lane_off);
 }
 
-// General path (frame edges, unaligned rows): byte loads, absent samples and
-// inputs read as the code of 0 + 0i.
-__device__ __forceinline__ void load_block_edge(uint2 (&raw)[8], const uint8_t* __restrict__ samples,
-                                                long long row_stride, int f, int N, int n0, int t0,
-                                                int t_end, bool active) {
+// General path (frame edges, unaligned rows, ragged tails): byte loads; absent
+// samples and inputs read as the code of 0 + 0i.
+__device__ __forceinline__ void load_pieces_edge(v4i (&raw)[4], const uint8_t* __restrict__ samples,
+                                                 long long row_stride, int f, int N, int n_first,
+                                                 int t_first, int t_end) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int t = t0 + k;
-    uint32_t w[2] = {0x88888888u, 0x88888888u};
-    if (active && t < t_end) {
-      const uint8_t* p = samples + (long long)t * row_stride + (long long)f * N + n0;
+  for (int k = 0; k < 4; ++k) {
+    const int t = t_first + 16 * k;
+    uint32_t w[4] = {0x88888888u, 0x88888888u, 0x88888888u, 0x88888888u};
+    if (t < t_end) {
+      const uint8_t* p = samples + (long long)t * row_stride + (long long)f * N + n_first;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        if (n0 + e < N) {
+      for (int e = 0; e < 16; ++e) {
+        if (n_first + e < N) {
           const uint32_t sh = 8 * (e & 3);
           w[e >> 2] = (w[e >> 2] & ~(0xFFu << sh)) | ((uint32_t)p[e] << sh);
         }
       }
     }
-    raw[k] = make_uint2(w[0], w[1]);
+    raw[k] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
   }
 }
 
-// Transpose the 8 x 8 byte block, split nibbles, convert and store the 8 rows'
-// segment q into an LDS operand block.
+// Split the nibbles of the four pieces, convert, and store them into the real
+// and imaginary planes of an LDS operand block (rows = times, as loaded).
 template <int FORM>
-__device__ __forceinline__ void stage_chunk(uint2 (&raw)[8], uint8_t* __restrict__ blk,
-                                            int row0, int q) {
-  transpose4x4(raw[0].x, raw[1].x, raw[2].x, raw[3].x);
-  transpose4x4(raw[4].x, raw[5].x, raw[6].x, raw[7].x);
-  transpose4x4(raw[0].y, raw[1].y, raw[2].y, raw[3].y);
-  transpose4x4(raw[4].y, raw[5].y, raw[6].y, raw[7].y);
+__device__ __forceinline__ void stage_pieces(const v4i (&raw)[4], uint8_t* __restrict__ blk,
+                                             const StageRole& sr) {
 #pragma unroll
-  for (int n = 0; n < 8; ++n) {
-    const uint32_t lo = n < 4 ? raw[n].x : raw[n - 4].y;  // times 0..3
-    const uint32_t hi = n < 4 ? raw[n + 4].x : raw[n].y;  // times 4..7
-    const uint32_t rl = (lo >> 4) & 0x0F0F0F0Fu, rh = (hi >> 4) & 0x0F0F0F0Fu;
-    const uint32_t ml = lo & 0x0F0F0F0Fu, mh = hi & 0x0F0F0F0Fu;
-    v4i seg;
-    if (FORM == FORM_I8) {
-      seg = v4i{(int)nib_to_i8(rl), (int)nib_to_i8(rh), (int)nib_to_i8(ml), (int)nib_to_i8(mh)};
-    } else {
-      seg = v4i{(int)nib_to_f8(rl), (int)nib_to_f8(rh), (int)nib_to_f8(ml), (int)nib_to_f8(mh)};
+  for (int k = 0; k < 4; ++k) {
+    v4i re, im;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const uint32_t w = (uint32_t)raw[k][d];
+      const uint32_t ur = (w >> 4) & 0x0F0F0F0Fu, um = w & 0x0F0F0F0Fu;
+      re[d] = (int)(FORM == FORM_I8 ? nib_to_i8(ur) : nib_to_f8(ur));
+      im[d] = (int)(FORM == FORM_I8 ? nib_to_i8(um) : nib_to_f8(um));
     }
-    *reinterpret_cast<v4i*>(blk + seg_off(row0 + n, q)) = seg;
+    const int off = (16 * k + sr.r0) * PROW + 16 * sr.seg;
+    *reinterpret_cast<v4i*>(blk + off) = re;
+    *reinterpret_cast<v4i*>(blk + PLANE + off) = im;
   }
 }
 
@@ -84,25 +86,33 @@ struct Acc<FORM_F8> {
 };
 
 // One chunk of MFMAs for a wave's 64 x 64 sub-tile (2 x 2 blocks of 32 x 32).
-// offA[a] / offB[b]: LDS byte offsets of this lane's rows (a = 0, 1 and
-// b = 0, 1) in the I and J blocks of the current buffer, including the
-// lane-half's first segment; k-step s adds a constant.
+// lds: the chunk's stage (I block at 0, J block at BLOCK_LDS); lane_rd: this
+// lane's transpose-read offset within a k-step (its row group and column);
+// rowA / rowB: the wave's first input row within the I and J blocks.
 template <int FORM>
-__device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, const int (&offA)[2],
-                                              const int (&offB)[2],
+__device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, int lane_rd,
+                                              int rowA, int rowB,
                                               typename Acc<FORM>::T (&re)[2][2],
                                               typename Acc<FORM>::T (&im)[2][2]) {
+  const uint8_t* pa = lds + lane_rd + rowA;
+  const uint8_t* pb = lds + BLOCK_LDS + lane_rd + rowB;
   if (FORM == FORM_I8) {
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
       v4i A[2], B[2], Y[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) A[a] = *reinterpret_cast<const v4i*>(lds + offA[a] + 32 * s);
+      for (int a = 0; a < 2; ++a) {
+        const v2i r = lds_tr8(pa + 16 * s * PROW + 32 * a);
+        const v2i m = lds_tr8(pa + PLANE + 16 * s * PROW + 32 * a);
+        A[a] = v4i{r.x, r.y, m.x, m.y};
+      }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        B[b] = *reinterpret_cast<const v4i*>(lds + offB[b] + 32 * s);
+        const v2i r = lds_tr8(pb + 16 * s * PROW + 32 * b);
+        const v2i m = lds_tr8(pb + PLANE + 16 * s * PROW + 32 * b);
+        B[b] = v4i{r.x, r.y, m.x, m.y};
         // [r r m m] -> [-m -m r r]
-        Y[b] = v4i{(int)neg_i8((uint32_t)B[b].z), (int)neg_i8((uint32_t)B[b].w), B[b].x, B[b].y};
+        Y[b] = v4i{(int)neg_i8((uint32_t)m.x), (int)neg_i8((uint32_t)m.y), r.x, r.y};
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -113,23 +123,26 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, c
         }
     }
   } else {
+    // a lane's 32 operand bytes: two groups of 8 samples (rows +0..7, +8..15)
 #pragma unroll
     for (int s = 0; s < KC / 32; ++s) {
       v8i A[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const v4i x0 = *reinterpret_cast<const v4i*>(lds + offA[a] + 64 * s);
-        const v4i x1 = *reinterpret_cast<const v4i*>(lds + offA[a] + 64 * s + 16);
-        A[a] = v8i{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        const uint8_t* q = pa + 32 * s * PROW + 32 * a;
+        const v2i r0 = lds_tr8(q), m0 = lds_tr8(q + PLANE);
+        const v2i r1 = lds_tr8(q + 8 * PROW), m1 = lds_tr8(q + PLANE + 8 * PROW);
+        A[a] = v8i{r0.x, r0.y, m0.x, m0.y, r1.x, r1.y, m1.x, m1.y};
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const v4i x0 = *reinterpret_cast<const v4i*>(lds + offB[b] + 64 * s);
-        const v4i x1 = *reinterpret_cast<const v4i*>(lds + offB[b] + 64 * s + 16);
-        const v8i B = v8i{x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+        const uint8_t* q = pb + 32 * s * PROW + 32 * b;
+        const v2i r0 = lds_tr8(q), m0 = lds_tr8(q + PLANE);
+        const v2i r1 = lds_tr8(q + 8 * PROW), m1 = lds_tr8(q + PLANE + 8 * PROW);
+        const v8i B = v8i{r0.x, r0.y, m0.x, m0.y, r1.x, r1.y, m1.x, m1.y};
         // FP8 negation flips the sign bit: [r r m m] -> [-m -m r r]
         const int sg = (int)0x80808080u;
-        const v8i Y = v8i{x0.z ^ sg, x0.w ^ sg, x0.x, x0.y, x1.z ^ sg, x1.w ^ sg, x1.x, x1.y};
+        const v8i Y = v8i{m0.x ^ sg, m0.y ^ sg, r0.x, r0.y, m1.x ^ sg, m1.y ^ sg, r1.x, r1.y};
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
           // format 0 = FP8 e4m3 for both operands; scale exponent 127 = 2^0
@@ -141,6 +154,17 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, c
       }
     }
   }
+}
+
+// This lane's transpose-read offset within a k-step: lanes of a 16-lane group
+// g address rows (j >> 1) at columns 8 * (j & 1) of a 16-input half; groups
+// 0/1 hold inputs 0..15 / 16..31 of a 32-row fragment, groups 2/3 the same
+// inputs eight (int8) or sixteen (FP8) samples later.
+template <int FORM>
+__device__ __forceinline__ int lane_read_offset(int lane) {
+  const int g = lane >> 4, j = lane & 15;
+  const int row = (FORM == FORM_I8 ? 8 : 16) * (g >> 1) + (j >> 1);
+  return row * PROW + 16 * (g & 1) + 8 * (j & 1);
 }
 
 __device__ __forceinline__ int to_i32(int x) { return x; }
@@ -208,26 +232,28 @@ struct TileCtx {
   uint8_t* lds;
   const uint8_t* rows;  // channel's rows at the tile's first sample (uniform)
   long long row_stride;
-  uint32_t lane_off;    // this thread's loads: 8*tg rows down, input n0
-  int sblk, ng, tg;     // staging role
-  int offA[2], offB[2];
+  uint32_t lane_off;    // this thread's loads: its row r0 and its 16 inputs
+  int sblk;             // staging block: 0 = I, 1 = J
+  StageRole sr;
+  int lane_rd, rowA, rowB;
   typename Acc<FORM>::T re[2][2], im[2][2];
+  __device__ __forceinline__ explicit TileCtx(int h) : sr(h) {}
 };
 
 // One chunk of the steady state: optionally load chunk `ld_chunk` into `ld`,
-// compute the chunk staged in `cur`, optionally stage `stg` into `nxt`, then
+// compute the chunk staged at `cur`, optionally stage `stg` into `nxt`, then
 // synchronise.  Straight-line code, so that the compiler can interleave the
 // staging arithmetic with the matrix instructions.
 template <int FORM, bool COMPUTE, bool LOAD, bool STAGE>
-__device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, uint2 (&stg)[8],
-                                            uint2 (&ld)[8], int ld_chunk) {
+__device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, const v4i (&stg)[4],
+                                            v4i (&ld)[4], int ld_chunk) {
   if (LOAD)
-    load_block_fast(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride,
-                    x.lane_off);
+    load_pieces_fast(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride,
+                     x.lane_off);
   // keep the loads at the top of the step: they have a whole step to land
   __builtin_amdgcn_sched_barrier(0);
-  if (COMPUTE) compute_chunk<FORM>(x.lds + cur, x.offA, x.offB, x.re, x.im);
-  if (STAGE) stage_chunk<FORM>(stg, x.lds + nxt + x.sblk * BLOCK_LDS, 8 * x.ng, x.tg);
+  if (COMPUTE) compute_chunk<FORM>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im);
+  if (STAGE) stage_pieces<FORM>(stg, x.lds + nxt + x.sblk * BLOCK_LDS, x.sr);
   __syncthreads();
 }
 
@@ -240,10 +266,10 @@ __device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, 
 template <int FORM, bool COMPUTE>
 __device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int nfast) {
   constexpr int B0 = 0, B1 = STAGE_LDS;
-  uint2 rawA[8], rawB[8];
-  load_block_fast(rawA, x.rows, x.row_stride, x.lane_off);
-  stage_chunk<FORM>(rawA, x.lds + B0 + x.sblk * BLOCK_LDS, 8 * x.ng, x.tg);
-  load_block_fast(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.lane_off);
+  v4i rawA[4], rawB[4];
+  load_pieces_fast(rawA, x.rows, x.row_stride, x.lane_off);
+  stage_pieces<FORM>(rawA, x.lds + B0 + x.sblk * BLOCK_LDS, x.sr);
+  load_pieces_fast(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.lane_off);
   __syncthreads();
   for (int c = 0; c < nsteady; c += 2) {
     steady_step<FORM, COMPUTE, true, true>(x, B0, B1, rawA, rawB, min(c + 2, nfast - 1));
@@ -257,7 +283,7 @@ __device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int
 // FP8 form: the caller keeps t_end - t_begin <= 65536, so that every f32
 // partial sum is an integer of magnitude <= 128 * 65536 = 2^23 (exact).
 //
-// ALIGNED: N % 8 == 0 and the sample rows are 8-byte aligned, so that whole
+// ALIGNED: N % 16 == 0 and the sample rows are 16-byte aligned, so that whole
 // chunks can take the fast loads.
 template <int FORM, bool ALIGNED>
 __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, int32_t* vis,
@@ -268,7 +294,7 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   const int nchunks = (len + KC - 1) / KC;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1, half = lane >> 5;
+  const int wr = wave >> 1, wc = wave & 1;
 
   // MFMA blocks of this wave that hold baselines of the triangle; a wave with
   // none (below the diagonal, or past N) skips the MFMAs, the others compute
@@ -280,40 +306,25 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     const int rs = rs0 + 32 * (ab >> 1), cs = cs0 + 32 * (ab & 1);
     if (rs < N && cs < N && cs >= rs) mask |= 1 << ab;
   }
-  int offA[2], offB[2];
-#pragma unroll
-  for (int x = 0; x < 2; ++x) {
-    const int seg0 = (FORM == FORM_I8) ? half : 2 * half;
-    offA[x] = seg_off(64 * wr + 32 * x + (lane & 31), seg0);
-    offB[x] = BLOCK_LDS + seg_off(64 * wc + 32 * x + (lane & 31), seg0);
-  }
 
-  // staging role: threads 0..127 load the I block, 128..255 the J block; in
-  // a 128-thread half, thread h covers inputs 8*(h >> 3).. and times 8*(h & 7)..
-  const int sblk = tid >> 7, h = tid & 127, tg = h & 7, ng = h >> 3;
-  const bool sactive = true;  // diagonal tiles: the J threads stage a copy of the I block
-  const int n0 = (sblk ? J : I) * BT + 8 * ng;
-  const bool inside_n = ALIGNED && n0 < N;  // N % 8 == 0: the 8 inputs are all present
-  // uniform row pointer of this channel at t_begin, and the lane's offset
+  // staging role: threads 0..127 load the I block, 128..255 the J block (a
+  // diagonal tile's J threads stage a copy of the I block: no branch)
+  const int sblk = tid >> 7;
+  TileCtx<FORM> x(tid & 127);
+  const int n_first = (sblk ? J : I) * BT + 16 * x.sr.seg;
+  // uniform row pointer of this channel at t_begin, and the lane's offset;
+  // inputs past N (edge tiles, N % 16 == 0) load a valid row instead: their
+  // LDS rows only reach baselines past N, which are never written
   const uint8_t* rows = samples + (long long)t_begin * row_stride + (long long)f * N;
-  const uint32_t lane_off = (uint32_t)(8 * tg) * (uint32_t)row_stride + (uint32_t)n0;
-
-  typedef typename Acc<FORM>::T V;
-  TileCtx<FORM> x;
   x.lds = lds;
   x.rows = rows;
   x.row_stride = row_stride;
-  // edge tiles (N % 8 == 0): inputs past N load a valid row instead; their LDS
-  // rows only reach baselines past N, which are never written
-  x.lane_off = (uint32_t)(8 * tg) * (uint32_t)row_stride + (uint32_t)(inside_n ? n0 : 0);
+  x.lane_off = (uint32_t)x.sr.r0 * (uint32_t)row_stride + (uint32_t)(n_first < N ? n_first : 0);
   x.sblk = sblk;
-  x.ng = ng;
-  x.tg = tg;
-#pragma unroll
-  for (int y = 0; y < 2; ++y) {
-    x.offA[y] = offA[y];
-    x.offB[y] = offB[y];
-  }
+  x.lane_rd = lane_read_offset<FORM>(lane);
+  x.rowA = 64 * wr;
+  x.rowB = 64 * wc;
+  typedef typename Acc<FORM>::T V;
 #pragma unroll
   for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -322,9 +333,7 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
       x.im[p][q] = V{};
     }
 
-  // Steady state over the chunks whose loads all lie inside the frame (the
-  // diagonal tile's J threads stage a second copy of the I block, which keeps
-  // the loop free of branches).
+  // Steady state over the chunks whose loads all lie inside the frame.
   const int nfast = ALIGNED ? len / KC : 0;
   const int nsteady = nfast & ~1;
   int c = 0;
@@ -338,17 +347,17 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
 
   // General loop: the remaining chunks (frame edges, ragged tail, short
   // ranges), one buffer flip per chunk.
-  uint2 raw[8];
+  v4i raw[4];
   auto load = [&](int cc) {
-    if (inside_n && (cc + 1) * KC <= len)
-      load_block_fast(raw, rows + (long long)cc * KC * row_stride, row_stride, lane_off);
+    if (ALIGNED && n_first < N && (cc + 1) * KC <= len)
+      load_pieces_fast(raw, rows + (long long)cc * KC * row_stride, row_stride, x.lane_off);
     else
-      load_block_edge(raw, samples, row_stride, f, N, n0, t_begin + cc * KC + 8 * tg, t_end,
-                      sactive);
+      load_pieces_edge(raw, samples, row_stride, f, N, n_first, t_begin + cc * KC + x.sr.r0,
+                       t_end);
   };
   if (c < nchunks) {
     load(c);
-    if (sactive) stage_chunk<FORM>(raw, lds + (c & 1) * STAGE_LDS + sblk * BLOCK_LDS, 8 * ng, tg);
+    stage_pieces<FORM>(raw, lds + (c & 1) * STAGE_LDS + sblk * BLOCK_LDS, x.sr);
     __syncthreads();
   }
   for (; c < nchunks; ++c) {
@@ -356,8 +365,8 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     uint8_t* nxt = lds + ((c + 1) & 1) * STAGE_LDS;
     const bool more = c + 1 < nchunks;
     if (more) load(c + 1);
-    if (mask) compute_chunk<FORM>(cur, offA, offB, x.re, x.im);
-    if (more && sactive) stage_chunk<FORM>(raw, nxt + sblk * BLOCK_LDS, 8 * ng, tg);
+    if (mask) compute_chunk<FORM>(cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im);
+    if (more) stage_pieces<FORM>(raw, nxt + sblk * BLOCK_LDS, x.sr);
     __syncthreads();
   }
   if (mask) write_blocks(vis, N, NB, f, rs0, cs0, lane, mask, mode, x.re, x.im);

@@ -3,26 +3,31 @@
 // The correlation of one channel is the complex Gram matrix V = X X^H of the
 // N x T sample matrix X (Sec. I; Sec. IV-C, "Full Correlation").  Writing
 // x = r + i m, the real and imaginary parts are two real contractions over the
-// same operand rows (Sec. II, Eq. (1) counts one complex MAC per baseline and
-// sample, i.e. four real MACs):
+// same operand rows (Eq. (1) counts one complex MAC per baseline and sample,
+// i.e. four real MACs):
 //
 //     Re V_ij = sum_t r_i r_j + m_i m_j       = sum_k A_i[k] A_j[k]
 //     Im V_ij = sum_t m_i r_j - r_i m_j       = sum_k A_i[k] Y_j[k]
 //
-// where a row A_n packs, for every block of 8 samples, the 8 real parts then
-// the 8 imaginary parts, and Y_n is the same row with each block rotated to
+// where a row A_n packs, for every group of 8 samples, the 8 real parts then
+// the 8 imaginary parts, and Y_n is the same row with each group rotated to
 // (-m, r).  Both are fed to the matrix cores (MFMA) as int8 (values -8..7) or
 // as FP8 e4m3 codes (exact for those values).
 //
-// Operand staging.  Global memory holds samples[t][f][n] (n fastest), while an
-// MFMA lane needs consecutive samples of one input.  Each workgroup therefore
-// loads a chunk of KC = 64 samples x 128 inputs with 8-byte loads, transposes
-// 8x8 byte blocks in registers (v_perm), splits the nibbles, removes the +8
-// offset and stores 16-byte segments [r(8 samples), m(8 samples)] into LDS.
-// A row of LDS holds the 8 segments of one input, padded to 144 bytes: eight
-// lanes reading eight consecutive rows at one segment then hit disjoint banks,
-// and the staging lanes, which write the 8 segments of a row side by side,
-// too.
+// Operand staging.  Global memory holds samples[t][f][n] (n fastest).  A
+// workgroup stages a chunk of KC = 64 samples of two blocks of 128 inputs:
+// every thread loads 16-byte row pieces (sixteen inputs at one time; eight
+// lanes cover a 128-byte row, so every load instruction reads whole cache
+// lines), splits the nibbles, removes the +8 offset and stores the real and
+// imaginary parts into two LDS planes laid out [t][n] as loaded, with no
+// transposition.  An MFMA lane needs eight consecutive samples of one input;
+// the LDS transpose read (ds_read_b64_tr_b8) delivers exactly that: within a
+// group of 16 lanes, lane i receives byte i & 7 of the 8 bytes addressed by
+// lanes 2k + (i >> 3), k = 0..7, so lanes addressing rows t0..t0+7 at
+// inputs n0..n0+15 receive, lane by lane, inputs n0+i at times t0..t0+7.
+// Plane rows are 144 bytes: the transpose reads (8 rows x 16 bytes per 16
+// lanes) and the staging writes (two rows 8 apart per 16 lanes) then hit
+// disjoint LDS banks.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,37 +35,22 @@
 
 namespace xeng {
 
+typedef int v2i __attribute__((ext_vector_type(2)));
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v8i __attribute__((ext_vector_type(8)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-constexpr int BT = 128;        // tile edge (inputs)
-constexpr int KC = 64;         // samples per staged chunk
-constexpr int ROWB = 2 * KC + 16;  // bytes per LDS row (r and m of KC samples, padded)
-constexpr int NTHREADS = 256;  // 4 waves: 2 x 2 wave tiles of 64 x 64
-constexpr int BLOCK_LDS = BT * ROWB;          // one operand block, bytes
-constexpr int STAGE_LDS = 2 * BLOCK_LDS;      // I block + J block
-constexpr int LDS_BYTES = 2 * STAGE_LDS;      // double buffered
+constexpr int BT = 128;                   // tile edge (inputs)
+constexpr int KC = 64;                    // samples per staged chunk
+constexpr int PROW = BT + 16;             // bytes per plane row (one time, 128 inputs, padded)
+constexpr int PLANE = KC * PROW;          // one plane (real or imaginary parts of a block)
+constexpr int NTHREADS = 256;             // 4 waves: 2 x 2 wave tiles of 64 x 64
+constexpr int BLOCK_LDS = 2 * PLANE;      // one operand block: real plane, imaginary plane
+constexpr int STAGE_LDS = 2 * BLOCK_LDS;  // I block + J block
+constexpr int LDS_BYTES = 2 * STAGE_LDS;  // double buffered
 
 enum Form { FORM_I8 = 0, FORM_F8 = 1 };
-
-// Byte offset of 16-byte segment q (0..7) of LDS row r.
-__device__ __forceinline__ int seg_off(int r, int q) { return r * ROWB + 16 * q; }
-
-// Transpose a 4x4 byte block: d[k] holds bytes (n0..n3) of time k; on return
-// d[n] holds bytes (t0..t3) of input n.
-__device__ __forceinline__ void transpose4x4(uint32_t& d0, uint32_t& d1, uint32_t& d2,
-                                             uint32_t& d3) {
-  const uint32_t s0 = __builtin_amdgcn_perm(d1, d0, 0x05010400u);
-  const uint32_t s1 = __builtin_amdgcn_perm(d1, d0, 0x07030602u);
-  const uint32_t s2 = __builtin_amdgcn_perm(d3, d2, 0x05010400u);
-  const uint32_t s3 = __builtin_amdgcn_perm(d3, d2, 0x07030602u);
-  d0 = __builtin_amdgcn_perm(s2, s0, 0x05040100u);
-  d1 = __builtin_amdgcn_perm(s2, s0, 0x07060302u);
-  d2 = __builtin_amdgcn_perm(s3, s1, 0x05040100u);
-  d3 = __builtin_amdgcn_perm(s3, s1, 0x07060302u);
-}
 
 // Offset-binary nibbles (u = value + 8, four per word) to signed int8 bytes:
 // per byte (u + 0x78) ^ 0x80 = u - 8 (mod 256); no carry crosses a byte.
@@ -85,6 +75,12 @@ __device__ __forceinline__ uint32_t nib_to_f8(uint32_t u) {
 // Negate four int8 bytes in [-8, 7]: ((~x ^ 0x80) + 1) ^ 0x80, carry-free.
 __device__ __forceinline__ uint32_t neg_i8(uint32_t x) {
   return ((x ^ 0x7F7F7F7Fu) + 0x01010101u) ^ 0x80808080u;
+}
+
+// LDS transpose read of 8 bytes (see above); p must be 8-byte aligned.
+__device__ __forceinline__ v2i lds_tr8(const uint8_t* p) {
+  typedef v2i __attribute__((address_space(3))) * lds_v2i;
+  return __builtin_amdgcn_ds_read_tr8_b64_v2i32((lds_v2i)(p));
 }
 
 }  // namespace xeng

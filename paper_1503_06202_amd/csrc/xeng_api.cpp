@@ -155,7 +155,9 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
 
   const int nt = (N + kTile - 1) / kTile;
   const long long tpc = tiles_per_channel(N);
-  const bool aligned = (N % 8 == 0) && ((reinterpret_cast<uintptr_t>(samples) & 7) == 0);
+  // fast loads: 16-byte row pieces, and per-lane offsets that fit 32 bits
+  const bool aligned = (N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples) & 15) == 0) &&
+                       ((long long)F * N <= (1LL << 26));
   // The FP8 form integrates at most XENG_F8_FLUSH_MAX samples per launch (f32
   // sums stay exact below 2^24); later launches add their int32 sums in
   // stream order.  The int8 form does the whole frame in one launch.
@@ -317,7 +319,8 @@ static int batch_upload(xeng_plan_t p, const uint8_t* const* samples, int32_t* c
     b.N = d.N;
     b.F = d.F;
     b.T = d.T;
-    b.aligned = (d.N % 8 == 0) && ((reinterpret_cast<uintptr_t>(samples[k]) & 7) == 0);
+    b.aligned = (d.N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples[k]) & 15) == 0) &&
+                ((long long)d.F * d.N <= (1LL << 26));
     b.zero = samples[k] ? p->inst_zero[k] : 0;
     b.pad = 0;
     p->uploaded[2 * k] = samples[k];

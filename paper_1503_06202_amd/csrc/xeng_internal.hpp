@@ -42,7 +42,7 @@ struct BatchInst {
   const uint8_t* samples;  // device [T][F][N]
   int32_t* vis;            // device [F][N(N+1)/2][2]
   int N, F, T;
-  int aligned;  // N % 8 == 0 and samples 8-byte aligned
+  int aligned;  // N % 16 == 0, samples 16-byte aligned, F * N <= 2^26
   int zero;     // clear vis before the launch (its tiles are integrated by atomic adds)
   int pad;
 };
