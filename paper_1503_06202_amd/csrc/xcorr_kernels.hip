@@ -13,11 +13,15 @@ namespace xeng {
 
 // Staging role of a thread within its block's 128 threads: it covers the 16
 // inputs 16*seg.. of the block at the four times r0, r0+16, r0+32, r0+48 of a
-// chunk, with r0 = 8*((h >> 3) & 1) + (h >> 4).  Eight consecutive lanes read
-// one 128-byte row; sixteen consecutive lanes write two plane rows 8 apart.
+// chunk, where r0 runs over 0..15 as q = h >> 3 does, in the order
+// 0,4,1,5,2,6,3,7,8,12,9,13,10,14,11,15.  Eight consecutive lanes read one
+// 128-byte row; sixteen consecutive lanes write two plane rows 4 apart.
 struct StageRole {
   int seg, r0;
-  __device__ __forceinline__ explicit StageRole(int h) : seg(h & 7), r0(8 * ((h >> 3) & 1) + (h >> 4)) {}
+  __device__ __forceinline__ explicit StageRole(int h) : seg(h & 7) {
+    const int q = h >> 3;
+    r0 = 4 * (q & 1) + ((q >> 1) & 3) + 8 * (q >> 3);
+  }
 };
 
 // Fast path: the four pieces lie inside the frame.  `rows` points at the
@@ -99,20 +103,24 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
   if (FORM == FORM_I8) {
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
+      // Operand rows are packed [m(8), r(8)] per 8 samples on both sides, so
+      // Re = A.B and Im = A.Y with Y = [r(8), -m(8)]: Y is B shifted by two
+      // registers, with the negated imaginary parts appended (no copies).
       v4i A[2], B[2], Y[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const v2i r = lds_tr8(pa + 16 * s * PROW + 32 * a);
         const v2i m = lds_tr8(pa + PLANE + 16 * s * PROW + 32 * a);
-        A[a] = v4i{r.x, r.y, m.x, m.y};
+        A[a] = v4i{m.x, m.y, r.x, r.y};
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const v2i r = lds_tr8(pb + 16 * s * PROW + 32 * b);
         const v2i m = lds_tr8(pb + PLANE + 16 * s * PROW + 32 * b);
-        B[b] = v4i{r.x, r.y, m.x, m.y};
-        // [r r m m] -> [-m -m r r]
-        Y[b] = v4i{(int)neg_i8((uint32_t)m.x), (int)neg_i8((uint32_t)m.y), r.x, r.y};
+        const v8i w = v8i{m.x, m.y, r.x, r.y, (int)neg_i8((uint32_t)m.x),
+                          (int)neg_i8((uint32_t)m.y), 0, 0};
+        B[b] = __builtin_shufflevector(w, w, 0, 1, 2, 3);
+        Y[b] = __builtin_shufflevector(w, w, 2, 3, 4, 5);
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
@@ -397,12 +405,14 @@ __global__ void __launch_bounds__(NTHREADS, 2)
     xcorr_batch_kernel(const BatchInst* __restrict__ insts, const BatchItem* __restrict__ items,
                        int nitems, int* counter) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
-  __shared__ int next;
+  // the next work item's index travels through the first LDS word, which is
+  // free between tiles (the LDS budget of two workgroups per CU is exact)
+  int* next = reinterpret_cast<int*>(lds);
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    if (threadIdx.x == 0) *next = atomicAdd(counter, 1);
     __syncthreads();
-    const int k = next;
-    __syncthreads();  // every thread has read `next` before thread 0 rewrites it
+    const int k = *next;
+    __syncthreads();  // every thread has read it before the LDS is reused
     if (k >= nitems) break;
     const BatchItem it = items[k];
     const BatchInst in = insts[it.inst];

@@ -25,9 +25,10 @@
 // group of 16 lanes, lane i receives byte i & 7 of the 8 bytes addressed by
 // lanes 2k + (i >> 3), k = 0..7, so lanes addressing rows t0..t0+7 at
 // inputs n0..n0+15 receive, lane by lane, inputs n0+i at times t0..t0+7.
-// Plane rows are 144 bytes: the transpose reads (8 rows x 16 bytes per 16
-// lanes) and the staging writes (two rows 8 apart per 16 lanes) then hit
-// disjoint LDS banks.
+// Plane rows are 160 bytes (40 banks of 4 bytes): the 32 lanes of a transpose
+// read pass (two 16-lane groups, 8 rows x 16 bytes each, 16 bytes apart) then
+// cover all 64 banks once, and so do the 16 lanes of a staging write pass
+// (two 128-byte rows 4 apart).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -43,7 +44,7 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int BT = 128;                   // tile edge (inputs)
 constexpr int KC = 64;                    // samples per staged chunk
-constexpr int PROW = BT + 16;             // bytes per plane row (one time, 128 inputs, padded)
+constexpr int PROW = BT + 32;             // bytes per plane row (one time, 128 inputs, padded)
 constexpr int PLANE = KC * PROW;          // one plane (real or imaginary parts of a block)
 constexpr int NTHREADS = 256;             // 4 waves: 2 x 2 wave tiles of 64 x 64
 constexpr int BLOCK_LDS = 2 * PLANE;      // one operand block: real plane, imaginary plane

@@ -89,14 +89,25 @@ long long tiles_per_channel(int N) {
   return nt * (nt + 1) / 2;
 }
 
-// Time slices per tile: one when the tiles alone fill the GPU several times
-// over, otherwise enough slices (of at least 4096 samples) to do so.
+// Time slices per tile.  With W tiles and `slots` resident workgroups, S
+// slices take ceil(W S / slots) rounds of 1/S of the work each; every extra
+// slice costs about 4% more (exact int32 atomic adds into vis, which must be
+// cleared first).  Pick the S that minimises ceil(W S / slots) / S * (1 +
+// 0.04 (S - 1)), keeping slices of at least 1024 samples.
 int auto_slices(long long tiles, int T, int cu_count) {
   const long long slots = (long long)cu_count * kOccupancy;
-  if (tiles >= 4 * slots) return 1;
-  long long want = (4 * slots + tiles - 1) / tiles;
-  long long by_t = std::max(1, T / 4096);
-  return (int)std::max(1LL, std::min(want, by_t));
+  const int smax = std::max(1, std::min(16, T / 1024));
+  int best = 1;
+  double best_cost = 1e300;
+  for (int S = 1; S <= smax; ++S) {
+    const long long rounds = (tiles * S + slots - 1) / slots;
+    const double cost = (double)rounds / S * (1.0 + 0.04 * (S - 1));
+    if (cost < best_cost - 1e-12) {
+      best_cost = cost;
+      best = S;
+    }
+  }
+  return best;
 }
 
 }  // namespace
