@@ -104,10 +104,14 @@ int xeng_correlate(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
  *   split_t  number of time slices per tile (1 = one workgroup per tile; more
  *            slices fill the GPU when there are few tiles, at the price of
  *            int32 atomic adds into vis, which are exact);
- *   chunk    reserved, must be 0.
- * Errors: XENG_EINVAL (NULL plan, negative values).
+ *   kernel   tile shape: 1 = 128 x 128 baselines per workgroup (two
+ *            workgroups per CU), 2 = 128 x 256 (one per CU; used only when
+ *            N % 16 == 0 and the samples are 16-byte aligned, else 1).
+ *            Automatic: 1, the faster of the two on gfx950 at every
+ *            measured size.
+ * Errors: XENG_EINVAL (NULL plan, negative split_t, kernel outside 0..2).
  */
-int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int chunk);
+int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel);
 
 /* Free a plan (NULL is accepted).  Waits for nothing: the caller must not
  * destroy a plan with work still in flight on its stream. */

@@ -33,6 +33,7 @@ struct xeng_plan_s {
   int form = XENG_FORM_I8;
   bool accumulate = false;
   int split_t = 0;  // 0 = automatic
+  int kernel = 0;   // 0 = automatic, 1 = 128 x 128 tiles, 2 = 128 x 256 tiles
   int cu_count = 0;
   std::string err;
 
@@ -89,13 +90,21 @@ long long tiles_per_channel(int N) {
   return nt * (nt + 1) / 2;
 }
 
+// 128 x 256 tiles (I, J) with J >= I / 2.
+long long wide_tiles_per_channel(int N) {
+  const long long nI = (N + kTile - 1) / kTile, nJ = (N + 2 * kTile - 1) / (2 * kTile);
+  long long t = 0;
+  for (long long I = 0; I < nI; ++I) t += nJ - I / 2;
+  return t;
+}
+
 // Time slices per tile.  With W tiles and `slots` resident workgroups, S
 // slices take ceil(W S / slots) rounds of 1/S of the work each; every extra
 // slice costs about 4% more (exact int32 atomic adds into vis, which must be
 // cleared first).  Pick the S that minimises ceil(W S / slots) / S * (1 +
 // 0.04 (S - 1)), keeping slices of at least 1024 samples.
-int auto_slices(long long tiles, int T, int cu_count) {
-  const long long slots = (long long)cu_count * kOccupancy;
+int auto_slices(long long tiles, int T, int cu_count, int occupancy = kOccupancy) {
+  const long long slots = (long long)cu_count * occupancy;
   const int smax = std::max(1, std::min(16, T / 1024));
   int best = 1;
   double best_cost = 1e300;
@@ -146,9 +155,10 @@ int xeng_plan(xeng_plan_t* out, int N, int F, int T_max, unsigned flags) {
   return XENG_OK;
 }
 
-int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int chunk) {
-  if (!p || split_t < 0 || chunk != 0) return XENG_EINVAL;
+int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel) {
+  if (!p || split_t < 0 || kernel < 0 || kernel > 2) return XENG_EINVAL;
   p->split_t = split_t;
+  p->kernel = kernel;
   return XENG_OK;
 }
 
@@ -165,17 +175,21 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
   hipStream_t s = static_cast<hipStream_t>(stream);
 
   const int nt = (N + kTile - 1) / kTile;
-  const long long tpc = tiles_per_channel(N);
   // fast loads: 16-byte row pieces, and per-lane offsets that fit 32 bits
   const bool aligned = (N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples) & 15) == 0) &&
                        ((long long)F * N <= (1LL << 26));
+  // wide tiles (128 x 256, one workgroup per CU) only on request and when
+  // the rows allow fast loads; 128 x 128 (two workgroups per CU) otherwise
+  const bool wide = aligned && p->kernel == 2;
+  const long long tpc = wide ? wide_tiles_per_channel(N) : tiles_per_channel(N);
+  const int occupancy = wide ? 1 : kOccupancy;
   // The FP8 form integrates at most XENG_F8_FLUSH_MAX samples per launch (f32
   // sums stay exact below 2^24); later launches add their int32 sums in
   // stream order.  The int8 form does the whole frame in one launch.
   const int seg = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : T;
   for (int t0 = 0; t0 < T; t0 += seg) {
     const int t1 = std::min(T, t0 + seg), len = t1 - t0;
-    int nslices = p->split_t > 0 ? p->split_t : auto_slices(tpc * F, len, p->cu_count);
+    int nslices = p->split_t > 0 ? p->split_t : auto_slices(tpc * F, len, p->cu_count, occupancy);
     nslices = std::min(nslices, (len + kChunk - 1) / kChunk);
     int slice_len = (len + nslices - 1) / nslices;
     slice_len = (slice_len + kChunk - 1) / kChunk * kChunk;
@@ -203,7 +217,7 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
     } else {
       a.write_mode = add ? xeng::WM_ADD : xeng::WM_STORE;
     }
-    hipError_t e = xeng::launch_tiles(a, p->form, aligned, s);
+    hipError_t e = wide ? xeng::launch_wide(a, p->form, s) : xeng::launch_tiles(a, p->form, aligned, s);
     if (e != hipSuccess) return hip_fail(p, e, "correlation kernel launch");
   }
   return XENG_OK;

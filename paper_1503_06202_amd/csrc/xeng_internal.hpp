@@ -25,6 +25,9 @@ struct TileArgs {
 };
 
 hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t stream);
+// 128 x 256 tiles, one workgroup per CU; needs N % 16 == 0 and 16-byte rows.
+// a.nt = ceil(N / 128), a.tiles_per_chan = wide tiles per channel.
+hipError_t launch_wide(const TileArgs& a, int form, hipStream_t stream);
 hipError_t launch_zero(int32_t* p, long long n, hipStream_t stream);
 
 // One work item of the batched persistent kernel.

@@ -64,7 +64,7 @@ class Plan:
     """
 
     def __init__(self, N: int, F: int, T_max: int, form: str = "i8", accumulate: bool = False,
-                 split_t: int = 0):
+                 split_t: int = 0, kernel: int = 0):
         if form not in FORMS:
             raise ValueError(f"form must be one of {sorted(FORMS)}")
         self.N, self.F, self.T_max, self.form, self.accumulate = N, F, T_max, form, accumulate
@@ -73,15 +73,17 @@ class Plan:
         _lib.check(_lib.lib().xeng_plan(ctypes.byref(h), int(N), int(F), int(T_max), flags),
                    "xeng_plan")
         self._h = h
-        if split_t:
-            self.set_tuning(split_t)
+        if split_t or kernel:
+            self.set_tuning(split_t, kernel)
 
     @property
     def handle(self) -> int:
         return self._h.value
 
-    def set_tuning(self, split_t: int = 0) -> None:
-        _lib.check(_lib.lib().xeng_plan_set_tuning(self._h, int(split_t), 0),
+    def set_tuning(self, split_t: int = 0, kernel: int = 0) -> None:
+        """split_t: time slices per tile (0 = automatic); kernel: 0 automatic,
+        1 = 128 x 128 tiles, 2 = 128 x 256 tiles (needs N % 16 == 0)."""
+        _lib.check(_lib.lib().xeng_plan_set_tuning(self._h, int(split_t), int(kernel)),
                    "xeng_plan_set_tuning")
 
     def correlate(self, samples: torch.Tensor, vis: Optional[torch.Tensor] = None,
@@ -118,11 +120,11 @@ class Plan:
 
 
 def correlate(samples: torch.Tensor, form: str = "i8", vis: Optional[torch.Tensor] = None,
-              accumulate: bool = False, split_t: int = 0,
+              accumulate: bool = False, split_t: int = 0, kernel: int = 0,
               stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
     """One-shot correlation of a frame (plans, runs and frees a plan)."""
     T, F, N = _check_samples(samples)
-    with Plan(N, F, T, form=form, accumulate=accumulate, split_t=split_t) as p:
+    with Plan(N, F, T, form=form, accumulate=accumulate, split_t=split_t, kernel=kernel) as p:
         return p.correlate(samples, vis, stream)
 
 

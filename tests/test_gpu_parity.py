@@ -17,10 +17,10 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
 
-def gpu(samples: np.ndarray, form="i8", split_t=0, vis=None, accumulate=False):
+def gpu(samples: np.ndarray, form="i8", split_t=0, vis=None, accumulate=False, kernel=0):
     T, F, N = samples.shape
     d = torch.from_numpy(np.ascontiguousarray(samples)).to(DEV)
-    with Plan(N, F, T, form=form, accumulate=accumulate, split_t=split_t) as p:
+    with Plan(N, F, T, form=form, accumulate=accumulate, split_t=split_t, kernel=kernel) as p:
         out = p.correlate(d, vis)
         torch.cuda.synchronize()
     return out.cpu().numpy()
@@ -53,6 +53,28 @@ def test_odd_shapes(N, T, form):
     s = rand_frame(N * 1000 + T, T, 2, N)
     print(f"odd N={N} F=2 T={T} form={form}", flush=True)
     assert np.array_equal(gpu(s, form), want(s))
+
+
+WIDE_SHAPES = [(16, 64), (48, 65), (144, 300), (256, 129), (272, 1000), (400, 64), (512, 257),
+               (640, 130)]
+
+
+@pytest.mark.parametrize("form", ["i8", "f8"])
+@pytest.mark.parametrize("N,T", WIDE_SHAPES)
+def test_wide_tiles(N, T, form):
+    # the 128 x 256 tile kernel forced on shapes that cover every tile row kind
+    s = rand_frame(N * 7 + T, T, 2, N)
+    print(f"wide N={N} F=2 T={T} form={form}", flush=True)
+    assert np.array_equal(gpu(s, form, kernel=2), want(s))
+
+
+@pytest.mark.parametrize("form", ["i8", "f8"])
+@pytest.mark.parametrize("split", [1, 3])
+def test_wide_vs_narrow_slices(split, form):
+    s = synth.gen_frame(768, 2, 1500, 12, "gauss+tone")
+    ref = want(s)
+    assert np.array_equal(gpu(s, form, split_t=split, kernel=2), ref)
+    assert np.array_equal(gpu(s, form, split_t=split, kernel=1), ref)
 
 
 @pytest.mark.parametrize("form", ["i8", "f8"])
@@ -195,10 +217,11 @@ def _check_sampled(s, got, count, seed):
 
 
 @pytest.mark.parametrize("form", ["i8", "f8"])
-def test_full_array_workload_sampled(full_array_frame, form):
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_full_array_workload_sampled(full_array_frame, form, kernel):
     w, s = full_array_frame
-    print(f"full_array N={w.N} F={w.F} T={w.T} form={form}", flush=True)
-    got = gpu(s, form)
+    print(f"full_array N={w.N} F={w.F} T={w.T} form={form} kernel={kernel}", flush=True)
+    got = gpu(s, form, kernel=kernel)
     _check_sampled(s, got, 3000, 1)
 
 
