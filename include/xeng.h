@@ -73,6 +73,10 @@ enum {
 #define XENG_T_EXACT_MAX 16777215 /* 2^24 - 1 */
 #define XENG_N_MAX 32768          /* inputs per instance, at most */
 #define XENG_F8_FLUSH_MAX 65536   /* FP8 form: samples per f32 partial sum, at most */
+#define XENG_I8_SEG_MAX 524288    /* int8 form, 128 x 128 tiles: samples integrated per launch
+                                     (or per batch slice), at most; the int32 sums then hold
+                                     16 V exactly.  Longer frames are split into launches
+                                     that add in stream order (or into more slices). */
 
 /* Library version: (major << 16) | minor. */
 int xeng_version(void);

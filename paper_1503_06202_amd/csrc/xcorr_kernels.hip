@@ -11,71 +11,116 @@
 
 namespace xeng {
 
-// Staging role of a thread within its block's 128 threads: it covers the 16
-// inputs 16*seg.. of the block at the four times r0, r0+16, r0+32, r0+48 of a
-// chunk, where r0 runs over 0..15 as q = h >> 3 does, in the order
-// 0,4,1,5,2,6,3,7,8,12,9,13,10,14,11,15.  Eight consecutive lanes read one
-// 128-byte row; sixteen consecutive lanes write two plane rows 4 apart.
+// Staging role of a thread.  Every thread stages four 16-byte row pieces of a
+// chunk (sixteen inputs at one time): pieces 0, 1 of the I block at times
+// rI, rI + 16 and pieces 2, 3 of the J block at times rJ, rJ + 16, with
+// rI = r0 + 32 h and rJ = r0 + 32 (1 - h) for the thread's half h of the
+// workgroup, so that every thread does the same work.  The inputs are
+// 16*seg.. of each block; r0 runs over 0..15 as q = (tid & 127) >> 3 does, in
+// the order 0,4,1,5,2,6,3,7,8,12,9,13,10,14,11,15.  Eight consecutive lanes
+// read one 128-byte row; sixteen consecutive lanes write two plane rows 4
+// apart.
 struct StageRole {
-  int seg, r0;
-  __device__ __forceinline__ explicit StageRole(int h) : seg(h & 7) {
-    const int q = h >> 3;
-    r0 = 4 * (q & 1) + ((q >> 1) & 3) + 8 * (q >> 3);
+  int seg, rI, rJ;
+  __device__ __forceinline__ explicit StageRole(int tid) : seg(tid & 7) {
+    const int q = (tid & 127) >> 3, h = tid >> 7;
+    const int r0 = 4 * (q & 1) + ((q >> 1) & 3) + 8 * (q >> 3);
+    rI = r0 + 32 * h;
+    rJ = r0 + 32 * (1 - h);
   }
 };
 
 // Fast path: the four pieces lie inside the frame.  `rows` points at the
-// chunk's first row of this channel (uniform across the workgroup); lane_off
-// adds the thread's row r0 and its inputs.
+// chunk's first row of this channel (uniform across the workgroup); offI /
+// offJ add the thread's first I / J row and its inputs.
 __device__ __forceinline__ void load_pieces_fast(v4i (&raw)[4], const uint8_t* __restrict__ rows,
-                                                 long long row_stride, uint32_t lane_off) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    raw[k] = *reinterpret_cast<const v4i*>(rows + (long long)(16 * k) * row_stride + lane_off);
+                                                 long long row_stride, uint32_t offI,
+                                                 uint32_t offJ) {
+  raw[0] = *reinterpret_cast<const v4i*>(rows + offI);
+  raw[1] = *reinterpret_cast<const v4i*>(rows + 16 * row_stride + offI);
+  raw[2] = *reinterpret_cast<const v4i*>(rows + offJ);
+  raw[3] = *reinterpret_cast<const v4i*>(rows + 16 * row_stride + offJ);
 }
 
-// General path (frame edges, unaligned rows, ragged tails): byte loads; absent
-// samples and inputs read as the code of 0 + 0i.
-__device__ __forceinline__ void load_pieces_edge(v4i (&raw)[4], const uint8_t* __restrict__ samples,
-                                                 long long row_stride, int f, int N, int n_first,
-                                                 int t_first, int t_end) {
+// General path (frame edges, unaligned rows, ragged tails): byte loads of the
+// piece at time t, inputs n_first..n_first+15; absent samples and inputs read
+// as the code of 0 + 0i.
+__device__ __forceinline__ v4i load_piece_edge(const uint8_t* __restrict__ samples,
+                                               long long row_stride, int f, int N, int n_first,
+                                               int t, int t_end) {
+  uint32_t w[4] = {0x88888888u, 0x88888888u, 0x88888888u, 0x88888888u};
+  if (t < t_end) {
+    const uint8_t* p = samples + (long long)t * row_stride + (long long)f * N + n_first;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int t = t_first + 16 * k;
-    uint32_t w[4] = {0x88888888u, 0x88888888u, 0x88888888u, 0x88888888u};
-    if (t < t_end) {
-      const uint8_t* p = samples + (long long)t * row_stride + (long long)f * N + n_first;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        if (n_first + e < N) {
-          const uint32_t sh = 8 * (e & 3);
-          w[e >> 2] = (w[e >> 2] & ~(0xFFu << sh)) | ((uint32_t)p[e] << sh);
-        }
+    for (int e = 0; e < 16; ++e) {
+      if (n_first + e < N) {
+        const uint32_t sh = 8 * (e & 3);
+        w[e >> 2] = (w[e >> 2] & ~(0xFFu << sh)) | ((uint32_t)p[e] << sh);
       }
     }
-    raw[k] = v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
   }
+  return v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
 }
 
-// Split the nibbles of the four pieces, convert, and store them into the real
-// and imaginary planes of an LDS operand block (rows = times, as loaded).
-template <int FORM>
-__device__ __forceinline__ void stage_pieces(const v4i (&raw)[4], uint8_t* __restrict__ blk,
-                                             const StageRole& sr) {
+// The four pieces of a thread by the general path; t_chunk is the chunk's
+// first time.
+__device__ __forceinline__ void load_pieces_edge(v4i (&raw)[4], const uint8_t* __restrict__ samples,
+                                                 long long row_stride, int f, int N, int nI,
+                                                 int nJ, const StageRole& sr, int t_chunk,
+                                                 int t_end) {
+  raw[0] = load_piece_edge(samples, row_stride, f, N, nI, t_chunk + sr.rI, t_end);
+  raw[1] = load_piece_edge(samples, row_stride, f, N, nI, t_chunk + sr.rI + 16, t_end);
+  raw[2] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ, t_end);
+  raw[3] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ + 16, t_end);
+}
+
+// Split the nibbles of a piece, convert, and store them into the real and
+// imaginary planes of an LDS operand block (rows = times, as loaded).
+//
+// FP8 form: e4m3 codes of the values on both sides.  Int8 form: the J block
+// (B operand) holds the values v = u - 8; the I block (A operand) holds 16 v,
+// which is the offset-binary nibble with its top bit flipped (the 4-bit two's
+// complement of v) placed in the top half of a byte: three operations per
+// word for both planes instead of seven.  The int8 sums are then 16 times the
+// visibilities (exact while |16 V| < 2^31, which the host guarantees by
+// limiting a launch to XENG_I8_SEG_MAX samples) and are shifted back at the
+// write.
+template <int FORM, bool ISIDE>
+__device__ __forceinline__ void stage_piece(const v4i& raw, uint8_t* __restrict__ dst) {
+  v4i re, im;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v4i re, im;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) {
-      const uint32_t w = (uint32_t)raw[k][d];
+  for (int d = 0; d < 4; ++d) {
+    const uint32_t w = (uint32_t)raw[d];
+    if (FORM == FORM_I8 && ISIDE) {
+      const uint32_t t = w ^ 0x88888888u;
+      re[d] = (int)(t & 0xF0F0F0F0u);
+      im[d] = (int)((t << 4) & 0xF0F0F0F0u);
+    } else {
       const uint32_t ur = (w >> 4) & 0x0F0F0F0Fu, um = w & 0x0F0F0F0Fu;
       re[d] = (int)(FORM == FORM_I8 ? nib_to_i8(ur) : nib_to_f8(ur));
       im[d] = (int)(FORM == FORM_I8 ? nib_to_i8(um) : nib_to_f8(um));
     }
-    const int off = (16 * k + sr.r0) * PROW + 16 * sr.seg;
-    *reinterpret_cast<v4i*>(blk + off) = re;
-    *reinterpret_cast<v4i*>(blk + PLANE + off) = im;
   }
+  *reinterpret_cast<v4i*>(dst) = re;
+  *reinterpret_cast<v4i*>(dst + PLANE) = im;
+}
+
+// Piece k of a thread into the stage at `stage` (I block at 0, J block at
+// BLOCK_LDS).
+template <int FORM>
+__device__ __forceinline__ void stage_piece_k(const v4i& raw, int k, uint8_t* __restrict__ stage,
+                                              const StageRole& sr) {
+  if (k < 2)
+    stage_piece<FORM, true>(raw, stage + (sr.rI + 16 * k) * PROW + 16 * sr.seg);
+  else
+    stage_piece<FORM, false>(raw, stage + BLOCK_LDS + (sr.rJ + 16 * (k - 2)) * PROW + 16 * sr.seg);
+}
+
+template <int FORM>
+__device__ __forceinline__ void stage_pieces(const v4i (&raw)[4], uint8_t* __restrict__ stage,
+                                             const StageRole& sr) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) stage_piece_k<FORM>(raw[k], k, stage, sr);
 }
 
 template <int FORM>
@@ -93,11 +138,17 @@ struct Acc<FORM_F8> {
 // lds: the chunk's stage (I block at 0, J block at BLOCK_LDS); lane_rd: this
 // lane's transpose-read offset within a k-step (its row group and column);
 // rowA / rowB: the wave's first input row within the I and J blocks.
-template <int FORM>
+//
+// With STAGE, the pieces `stg` of the next chunk are staged into the stage at
+// `blk` between the k-steps (one piece per int8 k-step, two per FP8 k-step): the staging
+// arithmetic then issues while the matrix cores work instead of after them.
+template <int FORM, bool STAGE = false>
 __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, int lane_rd,
                                               int rowA, int rowB,
                                               typename Acc<FORM>::T (&re)[2][2],
-                                              typename Acc<FORM>::T (&im)[2][2]) {
+                                              typename Acc<FORM>::T (&im)[2][2],
+                                              const v4i* stg = nullptr, uint8_t* blk = nullptr,
+                                              const StageRole* sr = nullptr) {
   const uint8_t* pa = lds + lane_rd + rowA;
   const uint8_t* pb = lds + BLOCK_LDS + lane_rd + rowB;
   if (FORM == FORM_I8) {
@@ -129,6 +180,7 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
           re[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], B[b], re[a][b], 0, 0, 0);
           im[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], Y[b], im[a][b], 0, 0, 0);
         }
+      if (STAGE) stage_piece_k<FORM>(stg[s], s, blk, *sr);
     }
   } else {
     // a lane's 32 operand bytes: two groups of 8 samples (rows +0..7, +8..15)
@@ -160,6 +212,10 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
                                                                      127, 0, 127);
         }
       }
+      if (STAGE) {
+        stage_piece_k<FORM>(stg[2 * s], 2 * s, blk, *sr);
+        stage_piece_k<FORM>(stg[2 * s + 1], 2 * s + 1, blk, *sr);
+      }
     }
   }
 }
@@ -177,6 +233,12 @@ __device__ __forceinline__ int lane_read_offset(int lane) {
 
 __device__ __forceinline__ int to_i32(int x) { return x; }
 __device__ __forceinline__ int to_i32(float x) { return (int)x; }  // exact: integral, |x| < 2^24
+
+// Accumulator to visibility for the 128 x 128 tiles: the int8 sums carry the
+// I-side factor 16 (a multiple of 16, so the shift is exact); FP8 sums are
+// integral f32.
+__device__ __forceinline__ int from_acc(int x) { return x >> 4; }
+__device__ __forceinline__ int from_acc(float x) { return (int)x; }
 
 // Write a wave's finished blocks into the packed triangle.  Offsets within a
 // channel are 32-bit (the plan limits N so that 2 N(N+1)/2 < 2^31).
@@ -197,8 +259,8 @@ __device__ __forceinline__ void write_blocks(int32_t* vis, int N, long long NB, 
         // b(i, j) = i N - i (i - 1) / 2 + (j - i)
         const int b = i * N - ((i * (i - 1)) >> 1) + (j - i);
         int32_t* p = base + 2 * b;
-        const int vr = to_i32(re[ai][bi][v]);
-        const int vi = (i == j) ? 0 : to_i32(im[ai][bi][v]);
+        const int vr = from_acc(re[ai][bi][v]);
+        const int vi = (i == j) ? 0 : from_acc(im[ai][bi][v]);
         if (mode == WM_STORE) {
           *reinterpret_cast<int2*>(p) = make_int2(vr, vi);
         } else if (mode == WM_ADD) {
@@ -240,8 +302,7 @@ struct TileCtx {
   uint8_t* lds;
   const uint8_t* rows;  // channel's rows at the tile's first sample (uniform)
   long long row_stride;
-  uint32_t lane_off;    // this thread's loads: its row r0 and its 16 inputs
-  int sblk;             // staging block: 0 = I, 1 = J
+  uint32_t offI, offJ;  // this thread's loads: its first I / J row and its inputs
   StageRole sr;
   int lane_rd, rowA, rowB;
   typename Acc<FORM>::T re[2][2], im[2][2];
@@ -256,12 +317,17 @@ template <int FORM, bool COMPUTE, bool LOAD, bool STAGE>
 __device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, const v4i (&stg)[4],
                                             v4i (&ld)[4], int ld_chunk) {
   if (LOAD)
-    load_pieces_fast(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride,
-                     x.lane_off);
+    load_pieces_fast(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride, x.offI,
+                     x.offJ);
   // keep the loads at the top of the step: they have a whole step to land
   __builtin_amdgcn_sched_barrier(0);
-  if (COMPUTE) compute_chunk<FORM>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im);
-  if (STAGE) stage_pieces<FORM>(stg, x.lds + nxt + x.sblk * BLOCK_LDS, x.sr);
+  if (COMPUTE && STAGE)
+    compute_chunk<FORM, true>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, stg,
+                              x.lds + nxt, &x.sr);
+  else if (COMPUTE)
+    compute_chunk<FORM>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im);
+  else if (STAGE)
+    stage_pieces<FORM>(stg, x.lds + nxt, x.sr);
   __syncthreads();
 }
 
@@ -275,9 +341,9 @@ template <int FORM, bool COMPUTE>
 __device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int nfast) {
   constexpr int B0 = 0, B1 = STAGE_LDS;
   v4i rawA[4], rawB[4];
-  load_pieces_fast(rawA, x.rows, x.row_stride, x.lane_off);
-  stage_pieces<FORM>(rawA, x.lds + B0 + x.sblk * BLOCK_LDS, x.sr);
-  load_pieces_fast(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.lane_off);
+  load_pieces_fast(rawA, x.rows, x.row_stride, x.offI, x.offJ);
+  stage_pieces<FORM>(rawA, x.lds + B0, x.sr);
+  load_pieces_fast(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.offI, x.offJ);
   __syncthreads();
   for (int c = 0; c < nsteady; c += 2) {
     steady_step<FORM, COMPUTE, true, true>(x, B0, B1, rawA, rawB, min(c + 2, nfast - 1));
@@ -315,20 +381,19 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     if (rs < N && cs < N && cs >= rs) mask |= 1 << ab;
   }
 
-  // staging role: threads 0..127 load the I block, 128..255 the J block (a
-  // diagonal tile's J threads stage a copy of the I block: no branch)
-  const int sblk = tid >> 7;
-  TileCtx<FORM> x(tid & 127);
-  const int n_first = (sblk ? J : I) * BT + 16 * x.sr.seg;
-  // uniform row pointer of this channel at t_begin, and the lane's offset;
-  // inputs past N (edge tiles, N % 16 == 0) load a valid row instead: their
-  // LDS rows only reach baselines past N, which are never written
+  // staging role: every thread stages two I pieces and two J pieces (a
+  // diagonal tile stages the same rows into both blocks: no branch)
+  TileCtx<FORM> x(tid);
+  const int nI = I * BT + 16 * x.sr.seg, nJ = J * BT + 16 * x.sr.seg;
+  // uniform row pointer of this channel at t_begin, and the lane's offsets;
+  // fast loads of inputs past N (edge tiles, N % 16 == 0) read a valid row
+  // instead: their LDS rows only reach baselines past N, never written
   const uint8_t* rows = samples + (long long)t_begin * row_stride + (long long)f * N;
   x.lds = lds;
   x.rows = rows;
   x.row_stride = row_stride;
-  x.lane_off = (uint32_t)x.sr.r0 * (uint32_t)row_stride + (uint32_t)(n_first < N ? n_first : 0);
-  x.sblk = sblk;
+  x.offI = (uint32_t)x.sr.rI * (uint32_t)row_stride + (uint32_t)(nI < N ? nI : 0);
+  x.offJ = (uint32_t)x.sr.rJ * (uint32_t)row_stride + (uint32_t)(nJ < N ? nJ : 0);
   x.lane_rd = lane_read_offset<FORM>(lane);
   x.rowA = 64 * wr;
   x.rowB = 64 * wc;
@@ -357,15 +422,14 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   // ranges), one buffer flip per chunk.
   v4i raw[4];
   auto load = [&](int cc) {
-    if (ALIGNED && n_first < N && (cc + 1) * KC <= len)
-      load_pieces_fast(raw, rows + (long long)cc * KC * row_stride, row_stride, x.lane_off);
+    if (ALIGNED && (cc + 1) * KC <= len)
+      load_pieces_fast(raw, rows + (long long)cc * KC * row_stride, row_stride, x.offI, x.offJ);
     else
-      load_pieces_edge(raw, samples, row_stride, f, N, n_first, t_begin + cc * KC + x.sr.r0,
-                       t_end);
+      load_pieces_edge(raw, samples, row_stride, f, N, nI, nJ, x.sr, t_begin + cc * KC, t_end);
   };
   if (c < nchunks) {
     load(c);
-    stage_pieces<FORM>(raw, lds + (c & 1) * STAGE_LDS + sblk * BLOCK_LDS, x.sr);
+    stage_pieces<FORM>(raw, lds + (c & 1) * STAGE_LDS, x.sr);
     __syncthreads();
   }
   for (; c < nchunks; ++c) {
@@ -374,7 +438,7 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     const bool more = c + 1 < nchunks;
     if (more) load(c + 1);
     if (mask) compute_chunk<FORM>(cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im);
-    if (more) stage_pieces<FORM>(raw, nxt + sblk * BLOCK_LDS, x.sr);
+    if (more) stage_pieces<FORM>(raw, nxt, x.sr);
     __syncthreads();
   }
   if (mask) write_blocks(vis, N, NB, f, rs0, cs0, lane, mask, mode, x.re, x.im);
@@ -494,12 +558,12 @@ __device__ __forceinline__ void wide_load_fast(WideRaw& raw, const uint8_t* __re
 __device__ __forceinline__ void wide_load_edge(WideRaw& raw, const uint8_t* __restrict__ samples,
                                                long long row_stride, int f, int N, int nI,
                                                int nJ, int tI, int tJ, int t_end) {
-  v4i tmp[4];
-  // reuse the 128-wide edge loader: it loads rows t, t+16, t+32, t+48
-  load_pieces_edge(tmp, samples, row_stride, f, N, nI, tI, t_end);
-  raw.i[0] = tmp[0];  // rows tI and tI + 32 (tI < 32 + ... see role)
-  raw.i[1] = tmp[2];
-  load_pieces_edge(raw.j, samples, row_stride, f, N, nJ, tJ, t_end);
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    raw.i[k] = load_piece_edge(samples, row_stride, f, N, nI, tI + 32 * k, t_end);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    raw.j[k] = load_piece_edge(samples, row_stride, f, N, nJ, tJ + 16 * k, t_end);
 }
 
 template <int FORM>

@@ -184,9 +184,10 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
   const long long tpc = wide ? wide_tiles_per_channel(N) : tiles_per_channel(N);
   const int occupancy = wide ? 1 : kOccupancy;
   // The FP8 form integrates at most XENG_F8_FLUSH_MAX samples per launch (f32
-  // sums stay exact below 2^24); later launches add their int32 sums in
-  // stream order.  The int8 form does the whole frame in one launch.
-  const int seg = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : T;
+  // sums stay exact below 2^24), the int8 form on 128 x 128 tiles at most
+  // XENG_I8_SEG_MAX (its int32 sums hold 16 V); later launches add their sums
+  // in stream order.  The wide int8 kernel does the whole frame in one launch.
+  const int seg = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : (wide ? T : XENG_I8_SEG_MAX);
   for (int t0 = 0; t0 < T; t0 += seg) {
     const int t1 = std::min(T, t0 + seg), len = t1 - t0;
     int nslices = p->split_t > 0 ? p->split_t : auto_slices(tpc * F, len, p->cu_count, occupancy);
@@ -252,9 +253,10 @@ int xeng_plan_batch(xeng_plan_t* out, const xeng_instance* descs, int count, uns
       const xeng_instance& d = descs[k];
       const int nt = (d.N + kTile - 1) / kTile;
       int S = d.split_t > 0 ? d.split_t : 1;
-      // FP8: no slice may integrate more than XENG_F8_FLUSH_MAX samples
-      if (p->form == XENG_FORM_F8)
-        S = std::max(S, (d.T + XENG_F8_FLUSH_MAX - 1) / XENG_F8_FLUSH_MAX);
+      // no slice may integrate more than XENG_F8_FLUSH_MAX (FP8) or
+      // XENG_I8_SEG_MAX (int8) samples
+      const int seg_max = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : XENG_I8_SEG_MAX;
+      S = std::max(S, (d.T + seg_max - 1) / seg_max);
       S = std::min(S, (d.T + kChunk - 1) / kChunk);
       int len = (d.T + S - 1) / S;
       len = (len + kChunk - 1) / kChunk * kChunk;

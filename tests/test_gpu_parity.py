@@ -161,6 +161,26 @@ def test_fp8_segment_boundary_random(form):
     assert np.array_equal(gpu(s, form), want(s))
 
 
+def test_int8_segment_boundary():
+    # the int8 128 x 128 kernels hold 16 V in int32 and split a frame into
+    # launches (and a batch instance into slices) of at most 2^19 samples
+    T, N = (1 << 19) + 3 * 64 + 5, 72
+    s = rand_frame(37, T, 1, N)
+    ref = want(s)
+    assert np.array_equal(gpu(s), ref)
+    d = torch.from_numpy(s).to(DEV)
+    vis = torch.empty(engine.vis_shape(N, 1), dtype=torch.int32, device=DEV)
+    with BatchPlan([(N, 1, T)], split_t=[1]) as bp:
+        bp.correlate([d], [vis])
+        torch.cuda.synchronize()
+    assert np.array_equal(vis.cpu().numpy(), ref)
+    # extremes on both sides of the boundary: -8-8i against 7+7i
+    s2 = np.where(np.arange(N)[None, None, :] % 2 == 0, 0x00, 0xFF).astype(np.uint8)
+    s2 = np.broadcast_to(s2, (T, 1, N)).copy()
+    s2[::3] ^= 0x0F
+    assert np.array_equal(gpu(s2), want(s2))
+
+
 def test_int32_boundary():
     # T = 2^24 - 1 of -8-8i: Re = 2,147,483,520, the largest exact integration
     T, N = (1 << 24) - 1, 8
