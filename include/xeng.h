@@ -72,11 +72,12 @@ enum {
 
 #define XENG_T_EXACT_MAX 16777215 /* 2^24 - 1 */
 #define XENG_N_MAX 32768          /* inputs per instance, at most */
-#define XENG_F8_FLUSH_MAX 65536   /* FP8 form: samples per f32 partial sum, at most */
+#define XENG_F8_FLUSH_MAX 32768   /* FP8 form: samples per f32 partial sum, at most (sums of
+                                     codes 0..15 stay below 2 * 225 * 32768 < 2^24) */
 #define XENG_I8_SEG_MAX 524288    /* int8 form, 128 x 128 tiles: samples integrated per launch
-                                     (or per batch slice), at most; the int32 sums then hold
-                                     16 V exactly.  Longer frames are split into launches
-                                     that add in stream order (or into more slices). */
+                                     (or per batch slice), at most; the int32 sums of codes
+                                     then stay below 2^31.  Longer frames are split into
+                                     launches that add in stream order (or into more slices). */
 
 /* Library version: (major << 16) | minor. */
 int xeng_version(void);
@@ -134,7 +135,8 @@ typedef struct xeng_instance {
     int N;       /* inputs */
     int F;       /* channels */
     int T;       /* samples integrated per call */
-    int split_t; /* time slices per tile; 0 = automatic (autotuner output goes here) */
+    int split_t; /* time slices per tile; 0 = automatic: one count for all such instances,
+                    chosen from the whole batch's tiles (autotuner output goes here) */
 } xeng_instance;
 
 /*

@@ -24,7 +24,7 @@ XENG_SHARED_VIS = 1 << 9
 
 XENG_T_EXACT_MAX = (1 << 24) - 1
 XENG_N_MAX = 32768
-XENG_F8_FLUSH_MAX = 65536
+XENG_F8_FLUSH_MAX = 32768
 XENG_I8_SEG_MAX = 524288
 
 # every symbol include/xeng.h declares

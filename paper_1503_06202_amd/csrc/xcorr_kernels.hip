@@ -74,32 +74,27 @@ __device__ __forceinline__ void load_pieces_edge(v4i (&raw)[4], const uint8_t* _
   raw[3] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ + 16, t_end);
 }
 
-// Split the nibbles of a piece, convert, and store them into the real and
+// Split the nibbles of a piece and store them, unchanged, into the real and
 // imaginary planes of an LDS operand block (rows = times, as loaded).
 //
-// FP8 form: e4m3 codes of the values on both sides.  Int8 form: the J block
-// (B operand) holds the values v = u - 8; the I block (A operand) holds 16 v,
-// which is the offset-binary nibble with its top bit flipped (the 4-bit two's
-// complement of v) placed in the top half of a byte: three operations per
-// word for both planes instead of seven.  The int8 sums are then 16 times the
-// visibilities (exact while |16 V| < 2^31, which the host guarantees by
-// limiting a launch to XENG_I8_SEG_MAX samples) and are shifted back at the
-// write.
-template <int FORM, bool ISIDE>
+// The planes hold the offset-binary codes u = v + 8 in 0..15, which both
+// matrix-core forms take as they are: as int8 they are the integers 0..15, and
+// as FP8 e4m3 bytes they are u * 2^-9 (the subnormals 0..7 and the first
+// binade 8..15 lie on one grid), which the MFMA's operand scale of 2^9 turns
+// back into u.  The MFMA therefore integrates products of codes; the offsets
+// are removed at the write from the per-input sums of the codes (see
+// TileSums): with S_n = sum_t u_n,
+//
+//   sum (u_i - 8)(u_j - 8) = sum u_i u_j - 8 S_i - 8 S_j + 64 T.
+//
+// Staging costs three operations per word for both planes.
 __device__ __forceinline__ void stage_piece(const v4i& raw, uint8_t* __restrict__ dst) {
   v4i re, im;
 #pragma unroll
   for (int d = 0; d < 4; ++d) {
     const uint32_t w = (uint32_t)raw[d];
-    if (FORM == FORM_I8 && ISIDE) {
-      const uint32_t t = w ^ 0x88888888u;
-      re[d] = (int)(t & 0xF0F0F0F0u);
-      im[d] = (int)((t << 4) & 0xF0F0F0F0u);
-    } else {
-      const uint32_t ur = (w >> 4) & 0x0F0F0F0Fu, um = w & 0x0F0F0F0Fu;
-      re[d] = (int)(FORM == FORM_I8 ? nib_to_i8(ur) : nib_to_f8(ur));
-      im[d] = (int)(FORM == FORM_I8 ? nib_to_i8(um) : nib_to_f8(um));
-    }
+    re[d] = (int)((w >> 4) & 0x0F0F0F0Fu);
+    im[d] = (int)(w & 0x0F0F0F0Fu);
   }
   *reinterpret_cast<v4i*>(dst) = re;
   *reinterpret_cast<v4i*>(dst + PLANE) = im;
@@ -107,20 +102,18 @@ __device__ __forceinline__ void stage_piece(const v4i& raw, uint8_t* __restrict_
 
 // Piece k of a thread into the stage at `stage` (I block at 0, J block at
 // BLOCK_LDS).
-template <int FORM>
 __device__ __forceinline__ void stage_piece_k(const v4i& raw, int k, uint8_t* __restrict__ stage,
                                               const StageRole& sr) {
   if (k < 2)
-    stage_piece<FORM, true>(raw, stage + (sr.rI + 16 * k) * PROW + 16 * sr.seg);
+    stage_piece(raw, stage + (sr.rI + 16 * k) * PROW + 16 * sr.seg);
   else
-    stage_piece<FORM, false>(raw, stage + BLOCK_LDS + (sr.rJ + 16 * (k - 2)) * PROW + 16 * sr.seg);
+    stage_piece(raw, stage + BLOCK_LDS + (sr.rJ + 16 * (k - 2)) * PROW + 16 * sr.seg);
 }
 
-template <int FORM>
 __device__ __forceinline__ void stage_pieces(const v4i (&raw)[4], uint8_t* __restrict__ stage,
                                              const StageRole& sr) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) stage_piece_k<FORM>(raw[k], k, stage, sr);
+  for (int k = 0; k < 4; ++k) stage_piece_k(raw[k], k, stage, sr);
 }
 
 template <int FORM>
@@ -134,61 +127,103 @@ struct Acc<FORM_F8> {
   typedef v16f T;
 };
 
-// One chunk of MFMAs for a wave's 64 x 64 sub-tile (2 x 2 blocks of 32 x 32).
+// Per-lane sums of codes over a tile's samples: of the real (r) and imaginary
+// (m) codes of one 32-input A fragment (rows) and one B fragment (columns).
+// Lane l sums input l & 31 of its fragment over the half of every k-step's
+// samples it holds (l >> 5 selects the half).  Every wave sums the A fragment
+// SA and the B fragment SB it is assigned, so that the four waves cover the
+// 128 rows and 128 columns of the tile once.
+struct TileSums {
+  uint32_t ar, am, br, bm;
+};
+
+// Sum of the four bytes of x, added to acc.
+__device__ __forceinline__ uint32_t bsum(int x, uint32_t acc) {
+  return __builtin_amdgcn_udot4((uint32_t)x, 0x01010101u, acc, false);
+}
+
+// FP8 operand scale: e8m0 exponent 127 + 9, i.e. 2^9 (code u reads u * 2^-9).
+constexpr int F8_SCALE = 127 + 9;
+
+// One chunk for a wave's 64 x 64 sub-tile (2 x 2 blocks of 32 x 32).
 // lds: the chunk's stage (I block at 0, J block at BLOCK_LDS); lane_rd: this
 // lane's transpose-read offset within a k-step (its row group and column);
 // rowA / rowB: the wave's first input row within the I and J blocks.
 //
-// With STAGE, the pieces `stg` of the next chunk are staged into the stage at
-// `blk` between the k-steps (one piece per int8 k-step, two per FP8 k-step): the staging
-// arithmetic then issues while the matrix cores work instead of after them.
-template <int FORM, bool STAGE = false>
+// COMPUTE: issue the MFMAs (a wave whose blocks all lie below the diagonal
+// only sums its fragments).  SA / SB: the A and B fragment this wave sums.
+// STAGE: the pieces `stg` of the next chunk are staged into the stage at `blk`
+// between the k-steps (one piece per int8 k-step, two per FP8 k-step), so
+// that the staging arithmetic issues while the matrix cores work.
+//
+// Operands.  Int8: a lane's 16 bytes pack [m(8), r(8)] for 8 samples; Re =
+// A.B and Im = A.Y with Y = [r(8), ~m(8)], where ~m = -m - 1 (one operation
+// instead of a negation; the extra -sum_t r_i is removed with the sums).  Y is
+// B's registers shifted by two, with ~m appended.  FP8: a lane's 32 bytes pack
+// [r(8), m(8), r(8), m(8)] for 16 samples; Y = [-m, r, -m, r], the negation
+// flipping the sign bit.
+//
+// SA = SB = -1: the fragments to sum are chosen at run time (sa, sb), all
+// four fragments are read, and the MFMAs run only when `mfma` is set.
+template <int FORM, bool COMPUTE, bool STAGE, int SA, int SB>
 __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, int lane_rd,
                                               int rowA, int rowB,
                                               typename Acc<FORM>::T (&re)[2][2],
-                                              typename Acc<FORM>::T (&im)[2][2],
+                                              typename Acc<FORM>::T (&im)[2][2], TileSums& sm,
                                               const v4i* stg = nullptr, uint8_t* blk = nullptr,
-                                              const StageRole* sr = nullptr) {
+                                              const StageRole* sr = nullptr, int sa = 0,
+                                              int sb = 0, bool mfma = true) {
+  constexpr bool RT = SA < 0;
   const uint8_t* pa = lds + lane_rd + rowA;
   const uint8_t* pb = lds + BLOCK_LDS + lane_rd + rowB;
   if (FORM == FORM_I8) {
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
-      // Operand rows are packed [m(8), r(8)] per 8 samples on both sides, so
-      // Re = A.B and Im = A.Y with Y = [r(8), -m(8)]: Y is B shifted by two
-      // registers, with the negated imaginary parts appended (no copies).
       v4i A[2], B[2], Y[2];
+      v2i ar[2], am[2], br[2], bm[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const v2i r = lds_tr8(pa + 16 * s * PROW + 32 * a);
-        const v2i m = lds_tr8(pa + PLANE + 16 * s * PROW + 32 * a);
-        A[a] = v4i{m.x, m.y, r.x, r.y};
+        if (!COMPUTE && !RT && a != SA) continue;
+        ar[a] = lds_tr8(pa + 16 * s * PROW + 32 * a);
+        am[a] = lds_tr8(pa + PLANE + 16 * s * PROW + 32 * a);
+        A[a] = v4i{am[a].x, am[a].y, ar[a].x, ar[a].y};
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const v2i r = lds_tr8(pb + 16 * s * PROW + 32 * b);
-        const v2i m = lds_tr8(pb + PLANE + 16 * s * PROW + 32 * b);
-        const v8i w = v8i{m.x, m.y, r.x, r.y, (int)neg_i8((uint32_t)m.x),
-                          (int)neg_i8((uint32_t)m.y), 0, 0};
+        if (!COMPUTE && !RT && b != SB) continue;
+        br[b] = lds_tr8(pb + 16 * s * PROW + 32 * b);
+        bm[b] = lds_tr8(pb + PLANE + 16 * s * PROW + 32 * b);
+        const v8i w = v8i{bm[b].x, bm[b].y, br[b].x, br[b].y, ~bm[b].x, ~bm[b].y, 0, 0};
         B[b] = __builtin_shufflevector(w, w, 0, 1, 2, 3);
         Y[b] = __builtin_shufflevector(w, w, 2, 3, 4, 5);
       }
+      if (COMPUTE && (!RT || mfma)) {
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          re[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], B[b], re[a][b], 0, 0, 0);
-          im[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], Y[b], im[a][b], 0, 0, 0);
-        }
-      if (STAGE) stage_piece_k<FORM>(stg[s], s, blk, *sr);
+          for (int b = 0; b < 2; ++b) {
+            re[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], B[b], re[a][b], 0, 0, 0);
+            im[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], Y[b], im[a][b], 0, 0, 0);
+          }
+      }
+      const v2i sar = RT ? (sa ? ar[1] : ar[0]) : ar[RT ? 0 : SA];
+      const v2i sam = RT ? (sa ? am[1] : am[0]) : am[RT ? 0 : SA];
+      const v2i sbr = RT ? (sb ? br[1] : br[0]) : br[RT ? 0 : SB];
+      const v2i sbm = RT ? (sb ? bm[1] : bm[0]) : bm[RT ? 0 : SB];
+      sm.ar = bsum(sar.y, bsum(sar.x, sm.ar));
+      sm.am = bsum(sam.y, bsum(sam.x, sm.am));
+      sm.br = bsum(sbr.y, bsum(sbr.x, sm.br));
+      sm.bm = bsum(sbm.y, bsum(sbm.x, sm.bm));
+      if (STAGE) stage_piece_k(stg[s], s, blk, *sr);
     }
   } else {
     // a lane's 32 operand bytes: two groups of 8 samples (rows +0..7, +8..15)
 #pragma unroll
     for (int s = 0; s < KC / 32; ++s) {
-      v8i A[2];
+      v8i A[2], B[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
+        if (!COMPUTE && !RT && a != SA) continue;
         const uint8_t* q = pa + 32 * s * PROW + 32 * a;
         const v2i r0 = lds_tr8(q), m0 = lds_tr8(q + PLANE);
         const v2i r1 = lds_tr8(q + 8 * PROW), m1 = lds_tr8(q + PLANE + 8 * PROW);
@@ -196,25 +231,38 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
+        if (!COMPUTE && !RT && b != SB) continue;
         const uint8_t* q = pb + 32 * s * PROW + 32 * b;
         const v2i r0 = lds_tr8(q), m0 = lds_tr8(q + PLANE);
         const v2i r1 = lds_tr8(q + 8 * PROW), m1 = lds_tr8(q + PLANE + 8 * PROW);
-        const v8i B = v8i{r0.x, r0.y, m0.x, m0.y, r1.x, r1.y, m1.x, m1.y};
-        // FP8 negation flips the sign bit: [r r m m] -> [-m -m r r]
-        const int sg = (int)0x80808080u;
-        const v8i Y = v8i{m0.x ^ sg, m0.y ^ sg, r0.x, r0.y, m1.x ^ sg, m1.y ^ sg, r1.x, r1.y};
+        B[b] = v8i{r0.x, r0.y, m0.x, m0.y, r1.x, r1.y, m1.x, m1.y};
+      }
+      if (COMPUTE && (!RT || mfma)) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          // format 0 = FP8 e4m3 for both operands; scale exponent 127 = 2^0
-          re[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[a], B, re[a][b], 0, 0, 0,
-                                                                     127, 0, 127);
-          im[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A[a], Y, im[a][b], 0, 0, 0,
-                                                                     127, 0, 127);
+        for (int b = 0; b < 2; ++b) {
+          // FP8 negation flips the sign bit: [r r m m] -> [-m -m r r]
+          const int sg = (int)0x80808080u;
+          const v8i Y = v8i{B[b][2] ^ sg, B[b][3] ^ sg, B[b][0], B[b][1],
+                            B[b][6] ^ sg, B[b][7] ^ sg, B[b][4], B[b][5]};
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            // format 0 = FP8 e4m3 for both operands; both scales 2^9
+            re[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                A[a], B[b], re[a][b], 0, 0, 0, F8_SCALE, 0, F8_SCALE);
+            im[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                A[a], Y, im[a][b], 0, 0, 0, F8_SCALE, 0, F8_SCALE);
+          }
         }
       }
+      const v8i sA = RT ? (sa ? A[1] : A[0]) : A[RT ? 0 : SA];
+      const v8i sB = RT ? (sb ? B[1] : B[0]) : B[RT ? 0 : SB];
+      sm.ar = bsum(sA[5], bsum(sA[4], bsum(sA[1], bsum(sA[0], sm.ar))));
+      sm.am = bsum(sA[7], bsum(sA[6], bsum(sA[3], bsum(sA[2], sm.am))));
+      sm.br = bsum(sB[5], bsum(sB[4], bsum(sB[1], bsum(sB[0], sm.br))));
+      sm.bm = bsum(sB[7], bsum(sB[6], bsum(sB[3], bsum(sB[2], sm.bm))));
       if (STAGE) {
-        stage_piece_k<FORM>(stg[2 * s], 2 * s, blk, *sr);
-        stage_piece_k<FORM>(stg[2 * s + 1], 2 * s + 1, blk, *sr);
+        stage_piece_k(stg[2 * s], 2 * s, blk, *sr);
+        stage_piece_k(stg[2 * s + 1], 2 * s + 1, blk, *sr);
       }
     }
   }
@@ -234,33 +282,52 @@ __device__ __forceinline__ int lane_read_offset(int lane) {
 __device__ __forceinline__ int to_i32(int x) { return x; }
 __device__ __forceinline__ int to_i32(float x) { return (int)x; }  // exact: integral, |x| < 2^24
 
-// Accumulator to visibility for the 128 x 128 tiles: the int8 sums carry the
-// I-side factor 16 (a multiple of 16, so the shift is exact); FP8 sums are
-// integral f32.
-__device__ __forceinline__ int from_acc(int x) { return x >> 4; }
-__device__ __forceinline__ int from_acc(float x) { return (int)x; }
+// Offset corrections of one input, added at the write (see stage_piece):
+// with S_r, S_m the sums of its real and imaginary codes over the T samples a
+// tile integrated (padding included: padded samples are codes 8 + 8i),
+//
+//   Re V_ij = Re_ij - 8 (S_r,i + S_m,i + S_r,j + S_m,j) + 128 T
+//   Im V_ij = Im_ij - 8 (S_m,i - S_r,i) + 8 (S_m,j - S_r,j)   [+ S_r,i for int8,
+//             whose Y carries ~m = -m - 1 instead of -m].
+// Row terms (A side) carry the constant 128 T.
+struct Corr {
+  int re, im;
+};
 
-// Write a wave's finished blocks into the packed triangle.  Offsets within a
-// channel are 32-bit (the plan limits N so that 2 N(N+1)/2 < 2^31).
+template <int FORM>
+__device__ __forceinline__ Corr row_corr(int sr, int sm, int T) {
+  return Corr{128 * T - 8 * (sr + sm), 8 * (sr - sm) + (FORM == FORM_I8 ? sr : 0)};
+}
+__device__ __forceinline__ Corr col_corr(int sr, int sm) {
+  return Corr{-8 * (sr + sm), 8 * (sm - sr)};
+}
+
+// Write a wave's finished blocks into the packed triangle, adding the offset
+// corrections (corr: 128 row terms, then 128 column terms, in LDS).  Offsets
+// within a channel are 32-bit (the plan limits N so that 2 N(N+1)/2 < 2^31).
 template <class V>
 __device__ __forceinline__ void write_blocks(int32_t* vis, int N, long long NB, int f, int rs0,
-                                             int cs0, int lane, int mask, int mode,
-                                             V (&re)[2][2], V (&im)[2][2]) {
+                                             int cs0, int lr0, int lc0, const int2* corr,
+                                             int lane, int mask, int mode, V (&re)[2][2],
+                                             V (&im)[2][2]) {
   int32_t* base = vis + 2 * (long long)f * NB;
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab) {
     const int ai = ab >> 1, bi = ab & 1;
     if (!(mask & (1 << ab))) continue;
     const int j = cs0 + 32 * bi + (lane & 31);
+    const int2 cj = corr[128 + lc0 + 32 * bi + (lane & 31)];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
-      const int i = rs0 + 32 * ai + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      const int di = 32 * ai + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      const int i = rs0 + di;
       if (i < N && j < N && j >= i) {
+        const int2 ci = corr[lr0 + di];
         // b(i, j) = i N - i (i - 1) / 2 + (j - i)
         const int b = i * N - ((i * (i - 1)) >> 1) + (j - i);
         int32_t* p = base + 2 * b;
-        const int vr = from_acc(re[ai][bi][v]);
-        const int vi = (i == j) ? 0 : from_acc(im[ai][bi][v]);
+        const int vr = to_i32(re[ai][bi][v]) + ci.x + cj.x;
+        const int vi = (i == j) ? 0 : to_i32(im[ai][bi][v]) + ci.y + cj.y;
         if (mode == WM_STORE) {
           *reinterpret_cast<int2*>(p) = make_int2(vr, vi);
         } else if (mode == WM_ADD) {
@@ -306,28 +373,23 @@ struct TileCtx {
   StageRole sr;
   int lane_rd, rowA, rowB;
   typename Acc<FORM>::T re[2][2], im[2][2];
+  TileSums sm;
   __device__ __forceinline__ explicit TileCtx(int h) : sr(h) {}
 };
 
 // One chunk of the steady state: optionally load chunk `ld_chunk` into `ld`,
-// compute the chunk staged at `cur`, optionally stage `stg` into `nxt`, then
+// compute the chunk staged at `cur` while staging `stg` into `nxt`, then
 // synchronise.  Straight-line code, so that the compiler can interleave the
 // staging arithmetic with the matrix instructions.
-template <int FORM, bool COMPUTE, bool LOAD, bool STAGE>
+template <int FORM, bool COMPUTE, int SA, int SB>
 __device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, const v4i (&stg)[4],
                                             v4i (&ld)[4], int ld_chunk) {
-  if (LOAD)
-    load_pieces_fast(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride, x.offI,
-                     x.offJ);
+  load_pieces_fast(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride, x.offI,
+                   x.offJ);
   // keep the loads at the top of the step: they have a whole step to land
   __builtin_amdgcn_sched_barrier(0);
-  if (COMPUTE && STAGE)
-    compute_chunk<FORM, true>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, stg,
-                              x.lds + nxt, &x.sr);
-  else if (COMPUTE)
-    compute_chunk<FORM>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im);
-  else if (STAGE)
-    stage_pieces<FORM>(stg, x.lds + nxt, x.sr);
+  compute_chunk<FORM, COMPUTE, true, SA, SB>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im,
+                                             x.sm, stg, x.lds + nxt, &x.sr);
   __syncthreads();
 }
 
@@ -337,37 +399,46 @@ __device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, 
 // (two register sets of raw samples).  Prefetches past the last fast chunk
 // reload that chunk, and what they stage is never computed, so the loop body
 // has no branch.
-template <int FORM, bool COMPUTE>
+template <int FORM, bool COMPUTE, int SA, int SB>
 __device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int nfast) {
   constexpr int B0 = 0, B1 = STAGE_LDS;
   v4i rawA[4], rawB[4];
   load_pieces_fast(rawA, x.rows, x.row_stride, x.offI, x.offJ);
-  stage_pieces<FORM>(rawA, x.lds + B0, x.sr);
+  stage_pieces(rawA, x.lds + B0, x.sr);
   load_pieces_fast(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.offI, x.offJ);
   __syncthreads();
   for (int c = 0; c < nsteady; c += 2) {
-    steady_step<FORM, COMPUTE, true, true>(x, B0, B1, rawA, rawB, min(c + 2, nfast - 1));
-    steady_step<FORM, COMPUTE, true, true>(x, B1, B0, rawB, rawA, min(c + 3, nfast - 1));
+    steady_step<FORM, COMPUTE, SA, SB>(x, B0, B1, rawA, rawB, min(c + 2, nfast - 1));
+    steady_step<FORM, COMPUTE, SA, SB>(x, B1, B0, rawB, rawA, min(c + 3, nfast - 1));
   }
 }
 
 // The work of one tile: baselines [I*128, I*128+128) x [J*128, J*128+128) of
 // channel f, integrated over samples [t_begin, t_end).  All 256 threads call
 // it; it ends with the tile written (mode) and the LDS free for reuse.
-// FP8 form: the caller keeps t_end - t_begin <= 65536, so that every f32
-// partial sum is an integer of magnitude <= 128 * 65536 = 2^23 (exact).
+// FP8 form: the caller keeps t_end - t_begin <= XENG_F8_FLUSH_MAX, so that every
+// f32 partial sum of codes is an integer below 2 * 225 * 32768 < 2^24 (exact).
+// Int8 form: the caller keeps t_end - t_begin <= XENG_I8_SEG_MAX, so that the
+// int32 sums of codes stay below 2 * 225 * 2^19 < 2^31.
 //
 // ALIGNED: N % 16 == 0 and the sample rows are 16-byte aligned, so that whole
 // chunks can take the fast loads.
+//
+// Wave (wr, wc) sums A fragment wc and B fragment wr (see TileSums).  The
+// fragment choice is a compile-time parameter of the steady loop, dispatched
+// once per tile on the wave index, so that the loop stays straight-line code.
 template <int FORM, bool ALIGNED>
 __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, int32_t* vis,
-                                          int N, long long row_stride, long long NB, int f,
-                                          int I, int J, int t_begin, int t_end, int mode,
-                                          uint8_t* lds) {
+                                            int N, long long row_stride, long long NB, int f,
+                                            int I, int J, int t_begin, int t_end, int mode,
+                                            uint8_t* lds) {
   const int len = t_end > t_begin ? t_end - t_begin : 0;
   const int nchunks = (len + KC - 1) / KC;
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index is uniform per wave: read it into a scalar register so that
+  // every branch on it is a uniform one
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
 
   // MFMA blocks of this wave that hold baselines of the triangle; a wave with
@@ -397,6 +468,7 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   x.lane_rd = lane_read_offset<FORM>(lane);
   x.rowA = 64 * wr;
   x.rowB = 64 * wc;
+  x.sm = TileSums{0u, 0u, 0u, 0u};
   typedef typename Acc<FORM>::T V;
 #pragma unroll
   for (int p = 0; p < 2; ++p)
@@ -411,10 +483,21 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   const int nsteady = nfast & ~1;
   int c = 0;
   if (nsteady >= 2) {
-    if (mask)
-      steady_chunks<FORM, true>(x, nsteady, nfast);
-    else
-      steady_chunks<FORM, false>(x, nsteady, nfast);
+    if (mask) {
+      switch (wave) {
+        case 0: steady_chunks<FORM, true, 0, 0>(x, nsteady, nfast); break;
+        case 1: steady_chunks<FORM, true, 1, 0>(x, nsteady, nfast); break;
+        case 2: steady_chunks<FORM, true, 0, 1>(x, nsteady, nfast); break;
+        default: steady_chunks<FORM, true, 1, 1>(x, nsteady, nfast); break;
+      }
+    } else {
+      switch (wave) {
+        case 0: steady_chunks<FORM, false, 0, 0>(x, nsteady, nfast); break;
+        case 1: steady_chunks<FORM, false, 1, 0>(x, nsteady, nfast); break;
+        case 2: steady_chunks<FORM, false, 0, 1>(x, nsteady, nfast); break;
+        default: steady_chunks<FORM, false, 1, 1>(x, nsteady, nfast); break;
+      }
+    }
     c = nsteady;
   }
 
@@ -429,7 +512,7 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   };
   if (c < nchunks) {
     load(c);
-    stage_pieces<FORM>(raw, lds + (c & 1) * STAGE_LDS, x.sr);
+    stage_pieces(raw, lds + (c & 1) * STAGE_LDS, x.sr);
     __syncthreads();
   }
   for (; c < nchunks; ++c) {
@@ -437,11 +520,40 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     uint8_t* nxt = lds + ((c + 1) & 1) * STAGE_LDS;
     const bool more = c + 1 < nchunks;
     if (more) load(c + 1);
-    if (mask) compute_chunk<FORM>(cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im);
-    if (more) stage_pieces<FORM>(raw, nxt, x.sr);
+    // the general loop reads all four fragments, sums the assigned ones
+    // through run-time selects and skips the MFMAs by a uniform flag (it
+    // carries few chunks)
+    compute_chunk<FORM, true, false, -1, -1>(cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, x.sm,
+                                             nullptr, nullptr, nullptr, wc, wr, mask != 0);
+    if (more) stage_pieces(raw, nxt, x.sr);
     __syncthreads();
   }
-  if (mask) write_blocks(vis, N, NB, f, rs0, cs0, lane, mask, mode, x.re, x.im);
+
+  // Per-input sums -> offset corrections, exchanged through the (now free)
+  // LDS: part[half][side][plane][128] holds each lane's partial sums, corr
+  // the row (side 0) and column (side 1) corrections.
+  int* part = reinterpret_cast<int*>(lds);
+  int2* corr = reinterpret_cast<int2*>(lds + 2 * 2 * 2 * BT * 4);
+  {
+    const int h = lane >> 5, l = lane & 31;
+    const int ra = 64 * wr + 32 * wc + l, cb = 64 * wc + 32 * wr + l;
+    part[((h * 2 + 0) * 2 + 0) * BT + ra] = (int)x.sm.ar;
+    part[((h * 2 + 0) * 2 + 1) * BT + ra] = (int)x.sm.am;
+    part[((h * 2 + 1) * 2 + 0) * BT + cb] = (int)x.sm.br;
+    part[((h * 2 + 1) * 2 + 1) * BT + cb] = (int)x.sm.bm;
+  }
+  __syncthreads();
+  {
+    const int side = tid >> 7, n = tid & (BT - 1);
+    const int sr = part[((0 * 2 + side) * 2 + 0) * BT + n] + part[((1 * 2 + side) * 2 + 0) * BT + n];
+    const int sm = part[((0 * 2 + side) * 2 + 1) * BT + n] + part[((1 * 2 + side) * 2 + 1) * BT + n];
+    const Corr cr = side == 0 ? row_corr<FORM>(sr, sm, nchunks * KC) : col_corr(sr, sm);
+    corr[side * BT + n] = make_int2(cr.re, cr.im);
+  }
+  __syncthreads();
+  if (mask)
+    write_blocks(vis, N, NB, f, rs0, cs0, 64 * wr, 64 * wc, corr, lane, mask, mode, x.re, x.im);
+  __syncthreads();  // the corrections are read before the LDS is reused
 }
 
 template <int FORM, bool ALIGNED>

@@ -10,25 +10,31 @@
 //     Im V_ij = sum_t m_i r_j - r_i m_j       = sum_k A_i[k] Y_j[k]
 //
 // where a row A_n packs, for every group of 8 samples, the 8 real parts then
-// the 8 imaginary parts, and Y_n is the same row with each group rotated to
-// (-m, r).  Both are fed to the matrix cores (MFMA) as int8 (values -8..7) or
-// as FP8 e4m3 codes (exact for those values).
+// the 8 imaginary parts (or the reverse), and Y_n is the same row with each
+// group rotated and one half negated.  Both are fed to the matrix cores
+// (MFMA) as int8 or as FP8 e4m3 bytes.
+//
+// The 128 x 128 kernels feed the offset-binary codes u = v + 8 themselves (int8
+// 0..15, or FP8 bytes that read u * 2^-9 and an operand scale of 2^9) and
+// remove the offsets at the write from per-input sums of the codes; the
+// 128 x 256 kernel converts the codes to the values -8..7 while staging
+// (nib_to_i8, nib_to_f8 below).
 //
 // Operand staging.  Global memory holds samples[t][f][n] (n fastest).  A
 // workgroup stages a chunk of KC = 64 samples of two blocks of 128 inputs:
 // every thread loads 16-byte row pieces (sixteen inputs at one time; eight
 // lanes cover a 128-byte row, so every load instruction reads whole cache
-// lines), splits the nibbles, removes the +8 offset and stores the real and
-// imaginary parts into two LDS planes laid out [t][n] as loaded, with no
-// transposition.  An MFMA lane needs eight consecutive samples of one input;
-// the LDS transpose read (ds_read_b64_tr_b8) delivers exactly that: within a
-// group of 16 lanes, lane i receives byte i & 7 of the 8 bytes addressed by
-// lanes 2k + (i >> 3), k = 0..7, so lanes addressing rows t0..t0+7 at
-// inputs n0..n0+15 receive, lane by lane, inputs n0+i at times t0..t0+7.
-// Plane rows are 160 bytes (40 banks of 4 bytes): the 32 lanes of a transpose
-// read pass (two 16-lane groups, 8 rows x 16 bytes each, 16 bytes apart) then
-// cover all 64 banks once, and so do the 16 lanes of a staging write pass
-// (two 128-byte rows 4 apart).
+// lines), splits the nibbles and stores the real and imaginary parts into two
+// LDS planes laid out [t][n] as loaded, with no transposition.  An MFMA lane
+// needs eight consecutive samples of one input; the LDS transpose read
+// (ds_read_b64_tr_b8) delivers exactly that: within a group of 16 lanes, lane
+// i receives byte i & 7 of the 8 bytes addressed by lanes 2k + (i >> 3),
+// k = 0..7, so lanes addressing rows t0..t0+7 at inputs n0..n0+15 receive,
+// lane by lane, inputs n0+i at times t0..t0+7.  Plane rows are 160 bytes (40
+// banks of 4 bytes): the 32 lanes of a transpose read pass (two 16-lane
+// groups, 8 rows x 16 bytes each, 16 bytes apart) then cover all 64 banks
+// once, and so do the 16 lanes of a staging write pass (two 128-byte rows 4
+// apart).
 #pragma once
 
 #include <hip/hip_runtime.h>

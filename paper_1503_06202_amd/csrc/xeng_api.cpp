@@ -119,6 +119,20 @@ int auto_slices(long long tiles, int T, int cu_count, int occupancy = kOccupancy
   return best;
 }
 
+// Compute units of the current device for a plan being built; without a
+// device (plans can be built and validated on a host with no GPU) the count
+// of an MI355X.  Only the automatic slice count depends on it.
+int cu_count_hint() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  return cus;
+}
+
 }  // namespace
 
 extern "C" {
@@ -184,9 +198,10 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
   const long long tpc = wide ? wide_tiles_per_channel(N) : tiles_per_channel(N);
   const int occupancy = wide ? 1 : kOccupancy;
   // The FP8 form integrates at most XENG_F8_FLUSH_MAX samples per launch (f32
-  // sums stay exact below 2^24), the int8 form on 128 x 128 tiles at most
-  // XENG_I8_SEG_MAX (its int32 sums hold 16 V); later launches add their sums
-  // in stream order.  The wide int8 kernel does the whole frame in one launch.
+  // sums of codes stay exact below 2^24), the int8 form on 128 x 128 tiles at
+  // most XENG_I8_SEG_MAX (int32 sums of codes below 2^31); later launches add
+  // their sums in stream order.  The wide int8 kernel does the whole frame in
+  // one launch.
   const int seg = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : (wide ? T : XENG_I8_SEG_MAX);
   for (int t0 = 0; t0 < T; t0 += seg) {
     const int t1 = std::min(T, t0 + seg), len = t1 - t0;
@@ -249,10 +264,15 @@ int xeng_plan_batch(xeng_plan_t* out, const xeng_instance* descs, int count, uns
       xeng::BatchItem it;
     };
     std::vector<Costed> work;
+    // automatic slices (split_t = 0): one count for the whole batch, from its
+    // total tiles, so that a launch of few instances still fills the GPU
+    long long batch_tiles = 0;
+    for (int k = 0; k < count; ++k) batch_tiles += descs[k].F * tiles_per_channel(descs[k].N);
+    const int s_auto = auto_slices(batch_tiles, XENG_T_EXACT_MAX, cu_count_hint());
     for (int k = 0; k < count; ++k) {
       const xeng_instance& d = descs[k];
       const int nt = (d.N + kTile - 1) / kTile;
-      int S = d.split_t > 0 ? d.split_t : 1;
+      int S = d.split_t > 0 ? d.split_t : std::max(1, std::min(s_auto, d.T / 1024));
       // no slice may integrate more than XENG_F8_FLUSH_MAX (FP8) or
       // XENG_I8_SEG_MAX (int8) samples
       const int seg_max = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : XENG_I8_SEG_MAX;

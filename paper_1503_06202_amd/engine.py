@@ -59,7 +59,7 @@ class Plan:
     """A correlation plan for frames of N inputs, F channels, T <= T_max samples.
 
     ``form`` is "i8" (int8 MFMA, int32 accumulators) or "f8" (FP8 e4m3 MFMA,
-    f32 partial sums flushed to int32 every <= 65536 samples).  With
+    f32 partial sums flushed to int32 every <= 32768 samples).  With
     ``accumulate`` the frame's sums are added to ``vis``.
     """
 

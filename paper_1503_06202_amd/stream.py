@@ -161,9 +161,11 @@ class RequestLoop:
 class GpuLauncher:
     """Runs batches of frames of one shape through ``libxeng.so``.
 
-    One batched plan covers ``slots`` identical instances (N, F, T); a launch
-    activates the slots that carry frames and leaves the rest idle.  Every
-    stream's accumulator lives on the GPU; frames add into it (shared,
+    There is one batched plan per batch size k = 1..``slots`` (k identical
+    instances (N, F, T)); a launch of k frames uses the plan of size k, whose
+    automatic time slices are chosen for k frames' worth of tiles, so that a
+    lone frame spreads over the whole GPU as well as a full batch does.
+    Every stream's accumulator lives on the GPU; frames add into it (shared,
     atomic) and ``dump`` enqueues an asynchronous copy to pinned host memory
     followed by a clear, all ordered on the launch stream.
     """
@@ -180,21 +182,30 @@ class GpuLauncher:
         self.graph = graph
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device)
-        self.plan = BatchPlan([(N, F, T)] * slots, form=form, accumulate=True, shared_vis=True)
+        self.plans = {k: BatchPlan([(N, F, T)] * k, form=form, accumulate=True, shared_vis=True)
+                      for k in range(1, slots + 1)}
         self.acc = [torch.zeros(vis_shape(N, F), dtype=torch.int32, device=self.device)
                     for _ in range(streams)]
 
     def launch(self, frames: List[Frame]):
         torch = self.torch
-        samples: List[Optional[Any]] = [None] * self.slots
-        vis: List[Optional[Any]] = [None] * self.slots
-        for k, f in enumerate(frames):
-            samples[k] = f.samples
-            vis[k] = self.acc[f.stream]
-        self.plan.correlate(samples, vis, stream=self.stream, graph=self.graph)
+        plan = self.plans[len(frames)]
+        samples = [f.samples for f in frames]
+        vis = [self.acc[f.stream] for f in frames]
+        plan.correlate(samples, vis, stream=self.stream, graph=self.graph)
         ev = torch.cuda.Event()
         ev.record(self.stream)
         return ev
+
+    def warm(self, samples) -> None:
+        """Run every plan once (capturing its graph) on ``samples``, then clear
+        the accumulators, so that no launch in a timed run pays for a capture."""
+        for k in range(1, self.slots + 1):
+            frames = [Frame(-1, 0, samples[i % len(samples)], 0.0) for i in range(k)]
+            self.launch(frames)
+        for a in self.acc:
+            a.zero_()
+        self.torch.cuda.synchronize(self.device)
 
     def ready(self, token) -> bool:
         return token.query()
@@ -212,4 +223,5 @@ class GpuLauncher:
         return (stream, host, ev)
 
     def close(self) -> None:
-        self.plan.close()
+        for p in self.plans.values():
+            p.close()

@@ -142,11 +142,14 @@ def test_repeatable_across_runs_and_forms():
 
 @pytest.mark.parametrize("form", ["i8", "f8"])
 def test_extreme_codes_long_integration(form):
-    # all -8-8i: every partial sum is as large as it gets (2^23 per 65536 samples)
+    # all -8-8i: the largest visibilities (128 T), carried by the offset terms
     T, N = 65536 + 640, 40
     s = np.zeros((T, 1, N), dtype=np.uint8)
     got = gpu(s, form)
     assert (got[..., 0] == 128 * T).all() and (got[..., 1] == 0).all()
+    # all 7+7i: the largest sums of codes (2 * 15 * 15 per sample)
+    got = gpu(np.full((T, 1, N), 0xFF, dtype=np.uint8), form)
+    assert (got[..., 0] == 98 * T).all() and (got[..., 1] == 0).all()
     # mixed extremes: -8-8i against 7+7i, the largest |Im| terms
     s2 = np.where(np.arange(N)[None, None, :] % 2 == 0, 0x00, 0xFF).astype(np.uint8)
     s2 = np.broadcast_to(s2, (T, 1, N)).copy()
