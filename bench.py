@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--form", default="i8", choices=["i8", "f8"])
     ap.add_argument("--split-t", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the MFMA-ceiling probe (measured MFMA throughput and clock on "
+                         "Gaussian-quantised operands, reported beside the data-sheet peak)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the frame's size (a known byte "
                          "count for scaling the HBM counters of a profiler run)")
@@ -150,6 +153,21 @@ def bench_stream(n_frames, torch):
     out["realtime_frame_period_ms"] = frame_period * 1e3
     launcher.close()
     return out
+
+
+def mfma_ceiling():
+    """The probe built beside the library (a child process): MFMA-only throughput
+    and shader clock on operands like the kernels', i.e. what the matrix cores
+    reach on this chip at its power limit."""
+    import subprocess
+
+    exe = os.path.join(ROOT, "paper_1503_06202_amd", "mfma_ceiling")
+    if not os.path.exists(exe):
+        return None
+    res = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    if res.returncode != 0:
+        return {"error": (res.stdout + res.stderr)[-300:]}
+    return json.loads(res.stdout.strip().splitlines()[-1])
 
 
 def cpu_baseline(frame, w):
@@ -276,6 +294,14 @@ def main():
         out["p99_frame_latency_ms"] = extra["stream"]["poisson_rho_0.9"]["p99_ms"]
     if extra:
         out["forms"] = extra
+    if not args.no_ceiling:
+        _log("bench: MFMA ceiling probe")
+        ceil = mfma_ceiling()
+        if ceil:
+            out["mfma_ceiling"] = ceil
+            key = "i8-codes" if args.form == "i8" else "f8-codes"
+            if key in ceil and ceil[key].get("tops"):
+                out["roofline"]["frac_of_measured_ceiling"] = achieved / ceil[key]["tops"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frame, w)
     print(json.dumps(out), flush=True)

@@ -1,7 +1,10 @@
 """Build the X-engine's HIP library ``libxeng.so`` in-tree for gfx950.
 
 The library is one shared object from the HIP kernels and the C ABI in
-``csrc/``; it exports the entry points declared in ``include/xeng.h``.
+``csrc/``; it exports the entry points declared in ``include/xeng.h``.  The
+benchmark's MFMA-ceiling probe (``csrc/mfma_ceiling.hip``) is built beside it
+as the executable ``mfma_ceiling``; it is a measurement tool, not part of the
+library.
 """
 from __future__ import annotations
 
@@ -13,6 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libxeng.so")
+CEILING = os.path.join(PKG, "mfma_ceiling")
 SOURCES = ("xcorr_kernels.hip", "xeng_api.cpp")
 ARCH = "gfx950"
 
@@ -32,20 +36,33 @@ def command(out: str = LIB) -> list:
             "-o", out] + [os.path.join(CSRC, s) for s in SOURCES]
 
 
-def build(quiet: bool = True) -> str:
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+def ceiling_command(out: str = CEILING) -> list:
+    return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-o", out, os.path.join(CSRC, "mfma_ceiling.hip")]
+
+
+def _run(cmd: list, what: str, quiet: bool) -> None:
     res = subprocess.run(cmd, capture_output=True, text=True)
     noise = "is not a recognized feature for this target"
     msg = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)
     if res.returncode != 0:
         sys.stderr.write(msg + "\n")
-        raise RuntimeError("libxeng build failed: " + " ".join(cmd))
+        raise RuntimeError(f"{what} build failed: " + " ".join(cmd))
     if msg.strip() and not quiet:
         print(msg)
+
+
+def build(quiet: bool = True) -> str:
+    tmp = LIB + ".tmp"
+    _run(command(tmp), "libxeng", quiet)
     os.replace(tmp, LIB)
+    tmp = CEILING + ".tmp"
+    _run(ceiling_command(tmp), "mfma_ceiling", quiet)
+    os.replace(tmp, CEILING)
     if not quiet:
         print("built", LIB)
+        print("built", CEILING)
     return LIB
 
 

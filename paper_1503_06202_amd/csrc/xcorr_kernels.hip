@@ -157,11 +157,13 @@ constexpr int F8_SCALE = 127 + 9;
 // that the staging arithmetic issues while the matrix cores work.
 //
 // Operands.  Int8: a lane's 16 bytes pack [m(8), r(8)] for 8 samples; Re =
-// A.B and Im = A.Y with Y = [r(8), ~m(8)], where ~m = -m - 1 (one operation
-// instead of a negation; the extra -sum_t r_i is removed with the sums).  Y is
-// B's registers shifted by two, with ~m appended.  FP8: a lane's 32 bytes pack
-// [r(8), m(8), r(8), m(8)] for 16 samples; Y = [-m, r, -m, r], the negation
-// flipping the sign bit.
+// A.B and Im = A.Y with Y = [r(8), 15 - m(8)] (15 - m = m ^ 15 per byte, one
+// operation; the extra 15 sum_t r_i is removed with the sums).  Every int8
+// operand byte thus lies in 0..15: small non-negative operands cost the
+// matrix cores markedly less power than signed ones, and the kernel runs at
+// the power limit.  Y is B's registers shifted by two, with 15 - m appended.
+// FP8: a lane's 32 bytes pack [r(8), m(8), r(8), m(8)] for 16 samples; Y =
+// [-m, r, -m, r], the negation flipping the sign bit.
 //
 // SA = SB = -1: the fragments to sum are chosen at run time (sa, sb), all
 // four fragments are read, and the MFMAs run only when `mfma` is set.
@@ -193,7 +195,8 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
         if (!COMPUTE && !RT && b != SB) continue;
         br[b] = lds_tr8(pb + 16 * s * PROW + 32 * b);
         bm[b] = lds_tr8(pb + PLANE + 16 * s * PROW + 32 * b);
-        const v8i w = v8i{bm[b].x, bm[b].y, br[b].x, br[b].y, ~bm[b].x, ~bm[b].y, 0, 0};
+        const int c15 = 0x0F0F0F0F;
+        const v8i w = v8i{bm[b].x, bm[b].y, br[b].x, br[b].y, bm[b].x ^ c15, bm[b].y ^ c15, 0, 0};
         B[b] = __builtin_shufflevector(w, w, 0, 1, 2, 3);
         Y[b] = __builtin_shufflevector(w, w, 2, 3, 4, 5);
       }
@@ -287,8 +290,8 @@ __device__ __forceinline__ int to_i32(float x) { return (int)x; }  // exact: int
 // tile integrated (padding included: padded samples are codes 8 + 8i),
 //
 //   Re V_ij = Re_ij - 8 (S_r,i + S_m,i + S_r,j + S_m,j) + 128 T
-//   Im V_ij = Im_ij - 8 (S_m,i - S_r,i) + 8 (S_m,j - S_r,j)   [+ S_r,i for int8,
-//             whose Y carries ~m = -m - 1 instead of -m].
+//   Im V_ij = Im_ij - 8 (S_m,i - S_r,i) + 8 (S_m,j - S_r,j)   [- 15 S_r,i for
+//             int8, whose Y carries 15 - m instead of -m].
 // Row terms (A side) carry the constant 128 T.
 struct Corr {
   int re, im;
@@ -296,7 +299,7 @@ struct Corr {
 
 template <int FORM>
 __device__ __forceinline__ Corr row_corr(int sr, int sm, int T) {
-  return Corr{128 * T - 8 * (sr + sm), 8 * (sr - sm) + (FORM == FORM_I8 ? sr : 0)};
+  return Corr{128 * T - 8 * (sr + sm), 8 * (sr - sm) - (FORM == FORM_I8 ? 15 * sr : 0)};
 }
 __device__ __forceinline__ Corr col_corr(int sr, int sm) {
   return Corr{-8 * (sr + sm), 8 * (sm - sr)};
