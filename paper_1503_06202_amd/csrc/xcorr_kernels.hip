@@ -133,13 +133,39 @@ struct Acc<FORM_F8> {
 // samples it holds (l >> 5 selects the half).  Every wave sums the A fragment
 // SA and the B fragment SB it is assigned, so that the four waves cover the
 // 128 rows and 128 columns of the tile once.
+//
+// The codes (0..15) are added bytewise, as packed words (one add of three
+// operands per two words: no carry leaves a byte while a byte holds at most
+// 17 codes), into b*.  flush() folds the four bytes of each and adds them to
+// the thread's 32-bit sums, which live in LDS, in the otherwise unused
+// padding of the first stage's plane rows (bytes 128..159 of every 160-byte
+// row; see sum_slot), so that they cost no registers.  It runs at most every
+// 16 codes per byte, i.e. every two chunks.
 struct TileSums {
-  uint32_t ar, am, br, bm;
+  uint32_t bar, bam, bbr, bbm;  // bytewise partial sums since the last flush
 };
 
-// Sum of the four bytes of x, added to acc.
-__device__ __forceinline__ uint32_t bsum(int x, uint32_t acc) {
-  return __builtin_amdgcn_udot4((uint32_t)x, 0x01010101u, acc, false);
+// This thread's four 32-bit sums (ar, am, br, bm): a 16-byte slot in the
+// padding of plane row tid / 2 of the first stage (rows 0..127 of its I-block
+// planes), bytes 128 + 16 (tid & 1) on.  Staging writes and transpose reads
+// touch bytes 0..127 of a row only.
+__device__ __forceinline__ uint32_t* sum_slot(uint8_t* lds) {
+  const int tid = threadIdx.x;
+  return reinterpret_cast<uint32_t*>(lds + (tid >> 1) * PROW + BT + 16 * (tid & 1));
+}
+
+__device__ __forceinline__ void flush_sums(TileSums& sm, uint8_t* lds) {
+  uint32_t* p = sum_slot(lds);
+  atomicAdd(p + 0, __builtin_amdgcn_udot4(sm.bar, 0x01010101u, 0u, false));
+  atomicAdd(p + 1, __builtin_amdgcn_udot4(sm.bam, 0x01010101u, 0u, false));
+  atomicAdd(p + 2, __builtin_amdgcn_udot4(sm.bbr, 0x01010101u, 0u, false));
+  atomicAdd(p + 3, __builtin_amdgcn_udot4(sm.bbm, 0x01010101u, 0u, false));
+  sm.bar = sm.bam = sm.bbr = sm.bbm = 0u;
+}
+
+// Two words of codes added bytewise into acc.
+__device__ __forceinline__ uint32_t badd(int x, int y, uint32_t acc) {
+  return acc + (uint32_t)x + (uint32_t)y;
 }
 
 // FP8 operand scale: e8m0 exponent 127 + 9, i.e. 2^9 (code u reads u * 2^-9).
@@ -213,10 +239,10 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
       const v2i sam = RT ? (sa ? am[1] : am[0]) : am[RT ? 0 : SA];
       const v2i sbr = RT ? (sb ? br[1] : br[0]) : br[RT ? 0 : SB];
       const v2i sbm = RT ? (sb ? bm[1] : bm[0]) : bm[RT ? 0 : SB];
-      sm.ar = bsum(sar.y, bsum(sar.x, sm.ar));
-      sm.am = bsum(sam.y, bsum(sam.x, sm.am));
-      sm.br = bsum(sbr.y, bsum(sbr.x, sm.br));
-      sm.bm = bsum(sbm.y, bsum(sbm.x, sm.bm));
+      sm.bar = badd(sar.x, sar.y, sm.bar);
+      sm.bam = badd(sam.x, sam.y, sm.bam);
+      sm.bbr = badd(sbr.x, sbr.y, sm.bbr);
+      sm.bbm = badd(sbm.x, sbm.y, sm.bbm);
       if (STAGE) stage_piece_k(stg[s], s, blk, *sr);
     }
   } else {
@@ -259,10 +285,10 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
       }
       const v8i sA = RT ? (sa ? A[1] : A[0]) : A[RT ? 0 : SA];
       const v8i sB = RT ? (sb ? B[1] : B[0]) : B[RT ? 0 : SB];
-      sm.ar = bsum(sA[5], bsum(sA[4], bsum(sA[1], bsum(sA[0], sm.ar))));
-      sm.am = bsum(sA[7], bsum(sA[6], bsum(sA[3], bsum(sA[2], sm.am))));
-      sm.br = bsum(sB[5], bsum(sB[4], bsum(sB[1], bsum(sB[0], sm.br))));
-      sm.bm = bsum(sB[7], bsum(sB[6], bsum(sB[3], bsum(sB[2], sm.bm))));
+      sm.bar = badd(sA[4], sA[5], badd(sA[0], sA[1], sm.bar));
+      sm.bam = badd(sA[6], sA[7], badd(sA[2], sA[3], sm.bam));
+      sm.bbr = badd(sB[4], sB[5], badd(sB[0], sB[1], sm.bbr));
+      sm.bbm = badd(sB[6], sB[7], badd(sB[2], sB[3], sm.bbm));
       if (STAGE) {
         stage_piece_k(stg[2 * s], 2 * s, blk, *sr);
         stage_piece_k(stg[2 * s + 1], 2 * s + 1, blk, *sr);
@@ -413,7 +439,46 @@ __device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int
   for (int c = 0; c < nsteady; c += 2) {
     steady_step<FORM, COMPUTE, SA, SB>(x, B0, B1, rawA, rawB, min(c + 2, nfast - 1));
     steady_step<FORM, COMPUTE, SA, SB>(x, B1, B0, rawB, rawA, min(c + 3, nfast - 1));
+    flush_sums(x.sm, x.lds);  // two chunks: 8 x 2 (int8) or 4 x 4 (FP8) words, <= 240 a byte
   }
+}
+
+// The same with one register set: chunk c + 1 loads at the start of chunk
+// c's step and is staged after chunk c's MFMAs.  Sixteen fewer registers,
+// for the persistent kernel, whose two tile paths share one allocation.
+template <int FORM, bool COMPUTE, int SA, int SB>
+__device__ __forceinline__ void steady_step1(TileCtx<FORM>& x, int cur, int nxt, v4i (&raw)[4],
+                                             int ld_chunk) {
+  load_pieces_fast(raw, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride, x.offI,
+                   x.offJ);
+  __builtin_amdgcn_sched_barrier(0);
+  compute_chunk<FORM, COMPUTE, false, SA, SB>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im,
+                                              x.sm);
+  __builtin_amdgcn_sched_barrier(0);
+  stage_pieces(raw, x.lds + nxt, x.sr);
+  __syncthreads();
+}
+
+template <int FORM, bool COMPUTE, int SA, int SB>
+__device__ __forceinline__ void steady_chunks1(TileCtx<FORM>& x, int nsteady, int nfast) {
+  constexpr int B0 = 0, B1 = STAGE_LDS;
+  v4i raw[4];
+  load_pieces_fast(raw, x.rows, x.row_stride, x.offI, x.offJ);
+  stage_pieces(raw, x.lds + B0, x.sr);
+  __syncthreads();
+  for (int c = 0; c < nsteady; c += 2) {
+    steady_step1<FORM, COMPUTE, SA, SB>(x, B0, B1, raw, min(c + 1, nfast - 1));
+    steady_step1<FORM, COMPUTE, SA, SB>(x, B1, B0, raw, min(c + 2, nfast - 1));
+    flush_sums(x.sm, x.lds);
+  }
+}
+
+template <int FORM, bool DEEP, bool COMPUTE, int SA, int SB>
+__device__ __forceinline__ void steady(TileCtx<FORM>& x, int nsteady, int nfast) {
+  if (DEEP)
+    steady_chunks<FORM, COMPUTE, SA, SB>(x, nsteady, nfast);
+  else
+    steady_chunks1<FORM, COMPUTE, SA, SB>(x, nsteady, nfast);
 }
 
 // The work of one tile: baselines [I*128, I*128+128) x [J*128, J*128+128) of
@@ -425,12 +490,12 @@ __device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int
 // int32 sums of codes stay below 2 * 225 * 2^19 < 2^31.
 //
 // ALIGNED: N % 16 == 0 and the sample rows are 16-byte aligned, so that whole
-// chunks can take the fast loads.
+// chunks can take the fast loads.  DEEP: prefetch two chunks ahead (else one).
 //
 // Wave (wr, wc) sums A fragment wc and B fragment wr (see TileSums).  The
 // fragment choice is a compile-time parameter of the steady loop, dispatched
 // once per tile on the wave index, so that the loop stays straight-line code.
-template <int FORM, bool ALIGNED>
+template <int FORM, bool ALIGNED, bool DEEP>
 __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, int32_t* vis,
                                             int N, long long row_stride, long long NB, int f,
                                             int I, int J, int t_begin, int t_end, int mode,
@@ -472,6 +537,9 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   x.rowA = 64 * wr;
   x.rowB = 64 * wc;
   x.sm = TileSums{0u, 0u, 0u, 0u};
+  // clear this thread's sums slot (it alone adds to it; a wave's LDS
+  // operations complete in order, and the previous tile ended on a barrier)
+  *reinterpret_cast<v4i*>(sum_slot(lds)) = v4i{0, 0, 0, 0};
   typedef typename Acc<FORM>::T V;
 #pragma unroll
   for (int p = 0; p < 2; ++p)
@@ -488,17 +556,17 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   if (nsteady >= 2) {
     if (mask) {
       switch (wave) {
-        case 0: steady_chunks<FORM, true, 0, 0>(x, nsteady, nfast); break;
-        case 1: steady_chunks<FORM, true, 1, 0>(x, nsteady, nfast); break;
-        case 2: steady_chunks<FORM, true, 0, 1>(x, nsteady, nfast); break;
-        default: steady_chunks<FORM, true, 1, 1>(x, nsteady, nfast); break;
+        case 0: steady<FORM, DEEP, true, 0, 0>(x, nsteady, nfast); break;
+        case 1: steady<FORM, DEEP, true, 1, 0>(x, nsteady, nfast); break;
+        case 2: steady<FORM, DEEP, true, 0, 1>(x, nsteady, nfast); break;
+        default: steady<FORM, DEEP, true, 1, 1>(x, nsteady, nfast); break;
       }
     } else {
       switch (wave) {
-        case 0: steady_chunks<FORM, false, 0, 0>(x, nsteady, nfast); break;
-        case 1: steady_chunks<FORM, false, 1, 0>(x, nsteady, nfast); break;
-        case 2: steady_chunks<FORM, false, 0, 1>(x, nsteady, nfast); break;
-        default: steady_chunks<FORM, false, 1, 1>(x, nsteady, nfast); break;
+        case 0: steady<FORM, DEEP, false, 0, 0>(x, nsteady, nfast); break;
+        case 1: steady<FORM, DEEP, false, 1, 0>(x, nsteady, nfast); break;
+        case 2: steady<FORM, DEEP, false, 0, 1>(x, nsteady, nfast); break;
+        default: steady<FORM, DEEP, false, 1, 1>(x, nsteady, nfast); break;
       }
     }
     c = nsteady;
@@ -528,22 +596,25 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     // carries few chunks)
     compute_chunk<FORM, true, false, -1, -1>(cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, x.sm,
                                              nullptr, nullptr, nullptr, wc, wr, mask != 0);
+    flush_sums(x.sm, lds);
     if (more) stage_pieces(raw, nxt, x.sr);
     __syncthreads();
   }
 
-  // Per-input sums -> offset corrections, exchanged through the (now free)
-  // LDS: part[half][side][plane][128] holds each lane's partial sums, corr
-  // the row (side 0) and column (side 1) corrections.
-  int* part = reinterpret_cast<int*>(lds);
-  int2* corr = reinterpret_cast<int2*>(lds + 2 * 2 * 2 * BT * 4);
+  // Per-input sums -> offset corrections, exchanged through the second
+  // stage's LDS (free now; the sums slots lie in the first stage):
+  // part[half][side][plane][128] holds each lane's partial sums, corr the row
+  // (side 0) and column (side 1) corrections.
+  int* part = reinterpret_cast<int*>(lds + STAGE_LDS);
+  int2* corr = reinterpret_cast<int2*>(lds + STAGE_LDS + 2 * 2 * 2 * BT * 4);
   {
+    const v4i sums = *reinterpret_cast<const v4i*>(sum_slot(lds));
     const int h = lane >> 5, l = lane & 31;
     const int ra = 64 * wr + 32 * wc + l, cb = 64 * wc + 32 * wr + l;
-    part[((h * 2 + 0) * 2 + 0) * BT + ra] = (int)x.sm.ar;
-    part[((h * 2 + 0) * 2 + 1) * BT + ra] = (int)x.sm.am;
-    part[((h * 2 + 1) * 2 + 0) * BT + cb] = (int)x.sm.br;
-    part[((h * 2 + 1) * 2 + 1) * BT + cb] = (int)x.sm.bm;
+    part[((h * 2 + 0) * 2 + 0) * BT + ra] = sums.x;
+    part[((h * 2 + 0) * 2 + 1) * BT + ra] = sums.y;
+    part[((h * 2 + 1) * 2 + 0) * BT + cb] = sums.z;
+    part[((h * 2 + 1) * 2 + 1) * BT + cb] = sums.w;
   }
   __syncthreads();
   {
@@ -572,8 +643,8 @@ __global__ void __launch_bounds__(NTHREADS, 2) xcorr_tile_kernel(TileArgs a) {
   const int t_begin = a.t0 + s * a.slice_len;
   const int t_end = min(a.t1, t_begin + a.slice_len);
   const long long NB = (long long)a.N * (a.N + 1) / 2;
-  tile_body<FORM, ALIGNED>(a.samples, a.vis, a.N, a.row_stride, NB, f, I, J, t_begin, t_end,
-                           a.write_mode, lds);
+  tile_body<FORM, ALIGNED, true>(a.samples, a.vis, a.N, a.row_stride, NB, f, I, J, t_begin,
+                                 t_end, a.write_mode, lds);
 }
 
 // Persistent batched kernel: every workgroup takes work items from a global
@@ -599,11 +670,11 @@ __global__ void __launch_bounds__(NTHREADS, 2)
     const long long NB = (long long)in.N * (in.N + 1) / 2;
     const long long stride = (long long)in.F * in.N;
     if (in.aligned)
-      tile_body<FORM, true>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J, it.t0, it.t1,
-                            it.mode, lds);
+      tile_body<FORM, true, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J, it.t0,
+                                   it.t1, it.mode, lds);
     else
-      tile_body<FORM, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J, it.t0, it.t1,
-                             it.mode, lds);
+      tile_body<FORM, false, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J,
+                                    it.t0, it.t1, it.mode, lds);
   }
 }
 
