@@ -32,14 +32,21 @@ struct StageRole {
 
 // Fast path: the four pieces lie inside the frame.  `rows` points at the
 // chunk's first row of this channel (uniform across the workgroup); offI /
-// offJ add the thread's first I / J row and its inputs.
+// offJ add the thread's first I / J row and its inputs.  Buffer loads: the
+// chunk's base goes into a scalar resource and the row offset of the second
+// piece into the scalar offset, so that a thread keeps two 32-bit offsets
+// instead of 64-bit addresses.  The host keeps F N <= 2^25 on this path, so
+// every offset (at most 64 rows of F N bytes) stays below 2^31.
 __device__ __forceinline__ void load_pieces_fast(v4i (&raw)[4], const uint8_t* __restrict__ rows,
                                                  long long row_stride, uint32_t offI,
                                                  uint32_t offJ) {
-  raw[0] = *reinterpret_cast<const v4i*>(rows + offI);
-  raw[1] = *reinterpret_cast<const v4i*>(rows + 16 * row_stride + offI);
-  raw[2] = *reinterpret_cast<const v4i*>(rows + offJ);
-  raw[3] = *reinterpret_cast<const v4i*>(rows + 16 * row_stride + offJ);
+  const __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc((void*)rows, (short)0, 0x7fffffff, 0x00020000);
+  const int s16 = (int)(16 * row_stride);
+  raw[0] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(r, (int)offI, 0, 0));
+  raw[1] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(r, (int)offI, s16, 0));
+  raw[2] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(r, (int)offJ, 0, 0));
+  raw[3] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(r, (int)offJ, s16, 0));
 }
 
 // General path (frame edges, unaligned rows, ragged tails): byte loads of the

@@ -191,7 +191,7 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
   const int nt = (N + kTile - 1) / kTile;
   // fast loads: 16-byte row pieces, and per-lane offsets that fit 32 bits
   const bool aligned = (N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples) & 15) == 0) &&
-                       ((long long)F * N <= (1LL << 26));
+                       ((long long)F * N <= (1LL << 25));
   // wide tiles (128 x 256, one workgroup per CU) only on request and when
   // the rows allow fast loads; 128 x 128 (two workgroups per CU) otherwise
   const bool wide = aligned && p->kernel == 2;
@@ -367,7 +367,7 @@ static int batch_upload(xeng_plan_t p, const uint8_t* const* samples, int32_t* c
     b.F = d.F;
     b.T = d.T;
     b.aligned = (d.N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples[k]) & 15) == 0) &&
-                ((long long)d.F * d.N <= (1LL << 26));
+                ((long long)d.F * d.N <= (1LL << 25));
     b.zero = samples[k] ? p->inst_zero[k] : 0;
     b.pad = 0;
     p->uploaded[2 * k] = samples[k];
