@@ -103,6 +103,11 @@ long long wide_tiles_per_channel(int N) {
 // slice costs about 4% more (exact int32 atomic adds into vis, which must be
 // cleared first).  Pick the S that minimises ceil(W S / slots) / S * (1 +
 // 0.04 (S - 1)), keeping slices of at least 1024 samples.
+double slice_cost(long long tiles, int S, long long slots) {
+  const long long rounds = (tiles * S + slots - 1) / slots;
+  return (double)rounds / S * (1.0 + 0.04 * (S - 1));
+}
+
 int auto_slices(long long tiles, int T, int cu_count, int occupancy = kOccupancy) {
   const long long slots = (long long)cu_count * occupancy;
   const int smax = std::max(1, std::min(16, T / 1024));
@@ -205,12 +210,37 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
   const int seg = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : (wide ? T : XENG_I8_SEG_MAX);
   for (int t0 = 0; t0 < T; t0 += seg) {
     const int t1 = std::min(T, t0 + seg), len = t1 - t0;
-    int nslices = p->split_t > 0 ? p->split_t : auto_slices(tpc * F, len, p->cu_count, occupancy);
+    const long long W = tpc * F;  // tiles of the launch
+    int nslices = p->split_t > 0 ? p->split_t : auto_slices(W, len, p->cu_count, occupancy);
     nslices = std::min(nslices, (len + kChunk - 1) / kChunk);
     int slice_len = (len + nslices - 1) / nslices;
     slice_len = (slice_len + kChunk - 1) / kChunk * kChunk;
     nslices = (len + slice_len - 1) / slice_len;
     const bool add = p->accumulate || t0 > 0;
+
+    // Automatic choice between uniform slices and a head/tail split: R full
+    // rounds of whole tiles (plain stores or adds), then the remaining tiles
+    // cut into S_t slices that fill one more round (atomic adds into a
+    // cleared region).  Same cost model as auto_slices.
+    const long long slots = (long long)p->cu_count * occupancy;
+    long long head = W;
+    int tail_slices = 0, tail_len = 0;
+    if (p->split_t == 0 && !wide && W > slots && W % slots != 0 && slots % 8 == 0) {
+      const long long R = W / slots, rem = W - R * slots;
+      const int smax = std::max(1, std::min(16, len / 1024));
+      int St = (int)std::min<long long>(smax, std::max<long long>(1, (slots + rem / 2) / rem));
+      int tl = (len + St - 1) / St;
+      tl = (tl + kChunk - 1) / kChunk * kChunk;
+      St = (len + tl - 1) / tl;
+      const double cost_tail = (double)R + slice_cost(rem, St, slots);
+      if (St > 1 && cost_tail < slice_cost(W, nslices, slots) - 1e-9) {
+        head = R * slots;
+        tail_slices = St;
+        tail_len = tl;
+        nslices = 1;
+        slice_len = len;
+      }
+    }
 
     xeng::TileArgs a;
     a.samples = samples;
@@ -224,6 +254,10 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
     a.nslices = nslices;
     a.slice_len = slice_len;
     a.row_stride = (long long)F * N;
+    a.head_tiles = (int)head;
+    a.tail_slices = tail_slices;
+    a.tail_len = tail_len;
+    a.tail_mode = xeng::WM_ATOMIC;
     if (nslices > 1) {
       a.write_mode = xeng::WM_ATOMIC;
       if (!add) {
@@ -232,6 +266,10 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
       }
     } else {
       a.write_mode = add ? xeng::WM_ADD : xeng::WM_STORE;
+    }
+    if (tail_slices > 0 && !add) {
+      hipError_t e = xeng::launch_zero_tiles(vis, N, (int)tpc, nt, (int)head, (int)(W - head), s);
+      if (e != hipSuccess) return hip_fail(p, e, "tail zero launch");
     }
     hipError_t e = wide ? xeng::launch_wide(a, p->form, s) : xeng::launch_tiles(a, p->form, aligned, s);
     if (e != hipSuccess) return hip_fail(p, e, "correlation kernel launch");

@@ -18,13 +18,25 @@ struct TileArgs {
   int t0, t1;          // integrated time range [t0, t1) of this launch
   int nt;              // tiles per edge, ceil(N / 128)
   int tiles_per_chan;  // nt (nt + 1) / 2
-  int nslices;         // time slices per tile
+  int nslices;         // time slices per head tile
   int slice_len;       // samples per slice, a multiple of 64
-  int write_mode;      // WM_STORE, WM_ADD or WM_ATOMIC
+  int write_mode;      // WM_STORE, WM_ADD or WM_ATOMIC: head items
   long long row_stride;  // F * N: bytes between consecutive time rows
+  // Tiles are numbered g = f * tiles_per_chan + p.  Head tiles [0, head_tiles)
+  // run as nslices slices each; the remaining (tail) tiles as tail_slices
+  // slices of tail_len samples each, adding with int32 atomics (tail_mode).
+  // Without a tail, head_tiles = F * tiles_per_chan and tail_slices = 0.
+  int head_tiles;
+  int tail_slices;
+  int tail_len;
+  int tail_mode;
 };
 
 hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t stream);
+// Clear the visibilities of tiles [first, first + count) (numbered as in
+// TileArgs) before their slices add into them.
+hipError_t launch_zero_tiles(int32_t* vis, int N, int tiles_per_chan, int nt, int first, int count,
+                             hipStream_t stream);
 // 128 x 256 tiles, one workgroup per CU; needs N % 16 == 0 and 16-byte rows.
 // a.nt = ceil(N / 128), a.tiles_per_chan = wide tiles per channel.
 hipError_t launch_wide(const TileArgs& a, int form, hipStream_t stream);

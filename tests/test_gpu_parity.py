@@ -164,6 +164,21 @@ def test_fp8_segment_boundary_random(form):
     assert np.array_equal(gpu(s, form), want(s))
 
 
+@pytest.mark.parametrize("form", ["i8", "f8"])
+def test_head_tail_split(form):
+    # 640 tiles on 512 resident workgroups: one round of whole tiles, then the
+    # remaining 128 tiles in time slices that add atomically into a cleared
+    # region (the automatic schedule when tiles do not divide into rounds)
+    T, F, N = 4096 + 3 * 64 + 5, 64, 512
+    s = rand_frame(41, T, F, N)
+    ref = want(s)
+    assert np.array_equal(gpu(s, form), ref)
+    # accumulating: whole tiles add, tail slices add atomically
+    vis = torch.from_numpy(np.full(ref.shape, 7, dtype=np.int32)).to(DEV)
+    got = gpu(s, form, vis=vis, accumulate=True)
+    assert np.array_equal(got, ref + 7)
+
+
 def test_int8_segment_boundary():
     # the int8 128 x 128 kernels hold 16 V in int32 and split a frame into
     # launches (and a batch instance into slices) of at most 2^19 samples
