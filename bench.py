@@ -48,9 +48,9 @@ def parse():
                          "count for scaling the HBM counters of a profiler run)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
-    ap.add_argument("--forms", default="f8,batched,stream",
+    ap.add_argument("--forms", default="f8,gated,batched,stream",
                     help="other forms reported beside the headline line (comma list of f8, "
-                         "batched, stream; empty for none)")
+                         "gated, batched, stream; empty for none)")
     ap.add_argument("--stream-frames", type=int, default=1000)
     return ap.parse_args()
 
@@ -80,6 +80,29 @@ def bench_fp8(d, w, steps, torch):
     ops = 8.0 * w.cmac / (ms / 1e3) / 1e12
     return {"workload": w.name, "ms_per_frame": ms, "cmac_per_s": w.cmac / (ms / 1e3),
             "tflops": ops, "pct_fp8_peak": 100.0 * ops / PEAK_TOPS["f8"]}
+
+
+def bench_gated(d, w, steps, torch, G=16, period=8192):
+    """Output gating on the same frame: each sample's phase in a period of
+    `period` samples picks one of G buffers (a pulsar-like fold); all G
+    buffers are written once per frame."""
+    import numpy as np
+
+    from paper_1503_06202_amd import Plan
+
+    t = np.arange(w.T, dtype=np.int64)
+    gate = ((t % period) * G // period).astype(np.int32)
+    vis = torch.empty((G,) + vis_shape_of(w), dtype=torch.int32, device=d.device)
+    with Plan(w.N, w.F, w.T, gates=G) as p:
+        ms = _time_calls(lambda: p.correlate_gated(d, gate, G, vis), steps, torch)
+    out_bytes = G * 8 * w.F * w.baselines
+    return {"workload": w.name, "gates": G, "period_samples": period, "ms_per_frame": ms,
+            "cmac_per_s": w.cmac / (ms / 1e3), "pct_int8_peak": 100.0 * 8.0 * w.cmac / (ms / 1e3) / 1e12 / PEAK_TOPS["i8"],
+            "output_bytes": out_bytes}
+
+
+def vis_shape_of(w):
+    return (w.F, w.baselines, 2)
 
 
 def bench_batched(steps, torch):
@@ -285,6 +308,9 @@ def main():
     if "f8" in forms:
         _log("bench: fp8 form")
         extra["fp8"] = bench_fp8(d, w, args.steps, torch)
+    if "gated" in forms:
+        _log("bench: gated form")
+        extra["gated"] = bench_gated(d, w, args.steps, torch)
     if "batched" in forms:
         _log("bench: batched form")
         extra["batched"] = bench_batched(max(3, args.steps // 4), torch)

@@ -74,6 +74,7 @@ enum {
 #define XENG_N_MAX 32768          /* inputs per instance, at most */
 #define XENG_F8_FLUSH_MAX 32768   /* FP8 form: samples per f32 partial sum, at most (sums of
                                      codes 0..15 stay below 2 * 225 * 32768 < 2^24) */
+#define XENG_G_MAX 65536          /* output gating: gate buffers per plan, at most */
 #define XENG_I8_SEG_MAX 524288    /* int8 form, 128 x 128 tiles: samples integrated per launch
                                      (or per batch slice), at most; the int32 sums of codes
                                      then stay below 2^31.  Longer frames are split into
@@ -117,6 +118,39 @@ int xeng_correlate(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
  * Errors: XENG_EINVAL (NULL plan, negative split_t, kernel outside 0..2).
  */
 int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel);
+
+/*
+ * Output gating (Sec. IV-C, "Output Gating"): the integration is partitioned
+ * into G sub-buffers by the time of each sample, e.g. by the phase of a
+ * pulsar's period or of an injected calibration signal, so that "on" and
+ * "off" visibilities are formed within one integration.
+ *
+ * xeng_plan_gated: a plan as xeng_plan (same N, F, T_max, flags; it also
+ * serves xeng_correlate) that can gate into up to G_max buffers.  It
+ * allocates, once, pinned host staging and device tables for the runs of a
+ * frame of T_max samples: about 8 (T_max + G_max) bytes of each.
+ * Errors: as xeng_plan; XENG_EINVAL for G_max outside 1..XENG_G_MAX;
+ * XENG_ENOMEM / XENG_EHIP when the tables cannot be allocated.
+ *
+ * xeng_correlate_gated: for every g in 0..G-1,
+ *   vis[g][f][b(i,j)] = sum over t with gate[t] == g of x[t][f][i] conj(x[t][f][j])
+ * (overwritten, or added with XENG_ACCUMULATE); samples whose gate is outside
+ * 0..G-1 are dropped.
+ *   gate   HOST array of T int32, read before the call returns.
+ *   vis    device int32 [G][F][N(N+1)/2][2] (gate-major), caller-owned.
+ * Asynchronous on `stream` like xeng_correlate.  The gate array becomes runs
+ * of equal gate, uploaded from the plan's staging; a call first waits for the
+ * previous call's upload to finish reading that staging.  Every (channel,
+ * tile, gate) is one work item that integrates all runs of its gate: cost
+ * grows with the number of runs only through their ragged edges (runs
+ * shorter than 64 samples are costly), and the output is written once.
+ * Errors: XENG_EINVAL (NULL pointers, N, F, T or G < 1), XENG_EPLAN (not a
+ * gated plan, G > G_max, N or F other than planned, T > T_max),
+ * XENG_EOVERFLOW (T > XENG_T_EXACT_MAX), XENG_EHIP.
+ */
+int xeng_plan_gated(xeng_plan_t *out, int N, int F, int T_max, int G_max, unsigned flags);
+int xeng_correlate_gated(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
+                         const int32_t *gate, int G, int32_t *vis, void *stream);
 
 /* Free a plan (NULL is accepted).  Waits for nothing: the caller must not
  * destroy a plan with work still in flight on its stream. */

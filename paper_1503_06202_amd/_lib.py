@@ -26,12 +26,13 @@ XENG_T_EXACT_MAX = (1 << 24) - 1
 XENG_N_MAX = 32768
 XENG_F8_FLUSH_MAX = 32768
 XENG_I8_SEG_MAX = 524288
+XENG_G_MAX = 65536
 
 # every symbol include/xeng.h declares
 EXPORTS = (
     "xeng_version", "xeng_strerror", "xeng_plan", "xeng_correlate", "xeng_plan_set_tuning",
     "xeng_destroy", "xeng_plan_error", "xeng_plan_batch", "xeng_correlate_batch",
-    "xeng_correlate_batch_graph",
+    "xeng_correlate_batch_graph", "xeng_plan_gated", "xeng_correlate_gated",
 )
 
 
@@ -75,6 +76,11 @@ def lib() -> ctypes.CDLL:
     L.xeng_correlate_batch.restype = ci
     L.xeng_correlate_batch_graph.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
     L.xeng_correlate_batch_graph.restype = ci
+    L.xeng_plan_gated.argtypes = [ctypes.POINTER(vp), ci, ci, ci, ci, ctypes.c_uint]
+    L.xeng_plan_gated.restype = ci
+    L.xeng_correlate_gated.argtypes = [vp, vp, ci, ci, ci, ctypes.POINTER(ctypes.c_int32), ci,
+                                       vp, vp]
+    L.xeng_correlate_gated.restype = ci
     _lib = L
     return L
 

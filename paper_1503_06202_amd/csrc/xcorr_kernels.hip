@@ -488,94 +488,46 @@ __device__ __forceinline__ void steady(TileCtx<FORM>& x, int nsteady, int nfast)
     steady_chunks1<FORM, COMPUTE, SA, SB>(x, nsteady, nfast);
 }
 
-// The work of one tile: baselines [I*128, I*128+128) x [J*128, J*128+128) of
-// channel f, integrated over samples [t_begin, t_end).  All 256 threads call
-// it; it ends with the tile written (mode) and the LDS free for reuse.
-// FP8 form: the caller keeps t_end - t_begin <= XENG_F8_FLUSH_MAX, so that every
-// f32 partial sum of codes is an integer below 2 * 225 * 32768 < 2^24 (exact).
-// Int8 form: the caller keeps t_end - t_begin <= XENG_I8_SEG_MAX, so that the
-// int32 sums of codes stay below 2 * 225 * 2^19 < 2^31.
-//
-// ALIGNED: N % 16 == 0 and the sample rows are 16-byte aligned, so that whole
-// chunks can take the fast loads.  DEEP: prefetch two chunks ahead (else one).
-//
-// Wave (wr, wc) sums A fragment wc and B fragment wr (see TileSums).  The
-// fragment choice is a compile-time parameter of the steady loop, dispatched
-// once per tile on the wave index, so that the loop stays straight-line code.
-template <int FORM, bool ALIGNED, bool DEEP>
-__device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, int32_t* vis,
-                                            int N, long long row_stride, long long NB, int f,
-                                            int I, int J, int t_begin, int t_end, int mode,
-                                            uint8_t* lds) {
+// Time ranges a tile integrates: one range [t0, t1) ...
+struct OneRange {
+  static constexpr bool kSingle = true;
+  int t0, t1;
+  __device__ __forceinline__ int count() const { return 1; }
+  __device__ __forceinline__ int begin(int) const { return t0; }
+  __device__ __forceinline__ int end(int) const { return t1; }
+};
+
+// ... or a list of runs [x, y) (output gating: the runs of one gate).
+struct RunList {
+  static constexpr bool kSingle = false;
+  const int2* runs;
+  int n;
+  __device__ __forceinline__ int count() const { return n; }
+  __device__ __forceinline__ int begin(int r) const { return runs[r].x; }
+  __device__ __forceinline__ int end(int r) const { return runs[r].y; }
+};
+
+// The chunks of one time range [t_begin, t_end) of a tile, added into the
+// tile's accumulators and sums.  Returns the samples it integrated, padding
+// of a ragged last chunk included (padded samples are the code 8 + 8i).
+// COMPUTE, SA, SB: as in compute_chunk (fixed per wave, see tile_body).
+template <int FORM, bool ALIGNED, bool DEEP, bool COMPUTE, int SA, int SB>
+__device__ __forceinline__ int tile_range(TileCtx<FORM>& x, const uint8_t* __restrict__ samples,
+                                          int N, int f, int nI, int nJ, int t_begin, int t_end,
+                                          uint8_t* lds) {
   const int len = t_end > t_begin ? t_end - t_begin : 0;
   const int nchunks = (len + KC - 1) / KC;
-
-  // the wave index is uniform per wave: read it into a scalar register so that
-  // every branch on it is a uniform one
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave >> 1, wc = wave & 1;
-
-  // MFMA blocks of this wave that hold baselines of the triangle; a wave with
-  // none (below the diagonal, or past N) skips the MFMAs, the others compute
-  // all four blocks and drop the surplus at the write.
-  const int rs0 = I * BT + 64 * wr, cs0 = J * BT + 64 * wc;
-  int mask = 0;
-#pragma unroll
-  for (int ab = 0; ab < 4; ++ab) {
-    const int rs = rs0 + 32 * (ab >> 1), cs = cs0 + 32 * (ab & 1);
-    if (rs < N && cs < N && cs >= rs) mask |= 1 << ab;
-  }
-
-  // staging role: every thread stages two I pieces and two J pieces (a
-  // diagonal tile stages the same rows into both blocks: no branch)
-  TileCtx<FORM> x(tid);
-  const int nI = I * BT + 16 * x.sr.seg, nJ = J * BT + 16 * x.sr.seg;
-  // uniform row pointer of this channel at t_begin, and the lane's offsets;
-  // fast loads of inputs past N (edge tiles, N % 16 == 0) read a valid row
-  // instead: their LDS rows only reach baselines past N, never written
+  const long long row_stride = x.row_stride;
+  // uniform row pointer of this channel at t_begin
   const uint8_t* rows = samples + (long long)t_begin * row_stride + (long long)f * N;
-  x.lds = lds;
   x.rows = rows;
-  x.row_stride = row_stride;
-  x.offI = (uint32_t)x.sr.rI * (uint32_t)row_stride + (uint32_t)(nI < N ? nI : 0);
-  x.offJ = (uint32_t)x.sr.rJ * (uint32_t)row_stride + (uint32_t)(nJ < N ? nJ : 0);
-  x.lane_rd = lane_read_offset<FORM>(lane);
-  x.rowA = 64 * wr;
-  x.rowB = 64 * wc;
-  x.sm = TileSums{0u, 0u, 0u, 0u};
-  // clear this thread's sums slot (it alone adds to it; a wave's LDS
-  // operations complete in order, and the previous tile ended on a barrier)
-  *reinterpret_cast<v4i*>(sum_slot(lds)) = v4i{0, 0, 0, 0};
-  typedef typename Acc<FORM>::T V;
-#pragma unroll
-  for (int p = 0; p < 2; ++p)
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      x.re[p][q] = V{};
-      x.im[p][q] = V{};
-    }
 
   // Steady state over the chunks whose loads all lie inside the frame.
   const int nfast = ALIGNED ? len / KC : 0;
   const int nsteady = nfast & ~1;
   int c = 0;
   if (nsteady >= 2) {
-    if (mask) {
-      switch (wave) {
-        case 0: steady<FORM, DEEP, true, 0, 0>(x, nsteady, nfast); break;
-        case 1: steady<FORM, DEEP, true, 1, 0>(x, nsteady, nfast); break;
-        case 2: steady<FORM, DEEP, true, 0, 1>(x, nsteady, nfast); break;
-        default: steady<FORM, DEEP, true, 1, 1>(x, nsteady, nfast); break;
-      }
-    } else {
-      switch (wave) {
-        case 0: steady<FORM, DEEP, false, 0, 0>(x, nsteady, nfast); break;
-        case 1: steady<FORM, DEEP, false, 1, 0>(x, nsteady, nfast); break;
-        case 2: steady<FORM, DEEP, false, 0, 1>(x, nsteady, nfast); break;
-        default: steady<FORM, DEEP, false, 1, 1>(x, nsteady, nfast); break;
-      }
-    }
+    steady<FORM, DEEP, COMPUTE, SA, SB>(x, nsteady, nfast);
     c = nsteady;
   }
 
@@ -598,20 +550,123 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     uint8_t* nxt = lds + ((c + 1) & 1) * STAGE_LDS;
     const bool more = c + 1 < nchunks;
     if (more) load(c + 1);
-    // the general loop reads all four fragments, sums the assigned ones
-    // through run-time selects and skips the MFMAs by a uniform flag (it
-    // carries few chunks)
-    compute_chunk<FORM, true, false, -1, -1>(cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, x.sm,
-                                             nullptr, nullptr, nullptr, wc, wr, mask != 0);
+    compute_chunk<FORM, COMPUTE, false, SA, SB>(cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, x.sm);
     flush_sums(x.sm, lds);
     if (more) stage_pieces(raw, nxt, x.sr);
     __syncthreads();
   }
+  return nchunks * KC;
+}
+
+// All ranges of a tile for one wave role.
+template <int FORM, bool ALIGNED, bool DEEP, bool COMPUTE, int SA, int SB, class Ranges>
+__device__ __forceinline__ int tile_ranges(TileCtx<FORM>& x, const uint8_t* __restrict__ samples,
+                                           int N, int f, int nI, int nJ, const Ranges& rg,
+                                           uint8_t* lds) {
+  if constexpr (Ranges::kSingle) {
+    return tile_range<FORM, ALIGNED, DEEP, COMPUTE, SA, SB>(x, samples, N, f, nI, nJ,
+                                                            rg.begin(0), rg.end(0), lds);
+  } else {
+    int teff = 0;
+    for (int r = 0; r < rg.count(); ++r)
+      teff += tile_range<FORM, ALIGNED, DEEP, COMPUTE, SA, SB>(x, samples, N, f, nI, nJ,
+                                                               rg.begin(r), rg.end(r), lds);
+    return teff;
+  }
+}
+
+// The work of one tile: baselines [I*128, I*128+128) x [J*128, J*128+128) of
+// channel f, integrated over the time ranges `rg`.  All 256 threads call it;
+// it ends with the tile written (mode) and the LDS free for reuse.
+// FP8 form: the caller keeps the integrated samples <= XENG_F8_FLUSH_MAX, so
+// that every f32 partial sum of codes is an integer below 2 * 225 * 32768 <
+// 2^24 (exact).  Int8 form: the caller keeps them <= XENG_I8_SEG_MAX, so that
+// the int32 sums of codes stay below 2 * 225 * 2^19 < 2^31.
+//
+// ALIGNED: N % 16 == 0 and the sample rows are 16-byte aligned, so that whole
+// chunks can take the fast loads.  DEEP: prefetch two chunks ahead (else one).
+//
+// Wave (wr, wc) sums A fragment wc and B fragment wr (see TileSums).  The
+// fragment choice is a compile-time parameter of the chunk loops, dispatched
+// once per tile on the wave index, so that the loops stay straight-line code.
+template <int FORM, bool ALIGNED, bool DEEP, class Ranges>
+__device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, int32_t* vis,
+                                          int N, long long row_stride, long long NB, int f,
+                                          int I, int J, const Ranges& rg, int mode,
+                                          uint8_t* lds) {
+  // the wave index is uniform per wave: read it into a scalar register so that
+  // every branch on it is a uniform one
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+
+  // MFMA blocks of this wave that hold baselines of the triangle; a wave with
+  // none (below the diagonal, or past N) skips the MFMAs, the others compute
+  // all four blocks and drop the surplus at the write.
+  const int rs0 = I * BT + 64 * wr, cs0 = J * BT + 64 * wc;
+  int mask = 0;
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab) {
+    const int rs = rs0 + 32 * (ab >> 1), cs = cs0 + 32 * (ab & 1);
+    if (rs < N && cs < N && cs >= rs) mask |= 1 << ab;
+  }
+
+  // staging role: every thread stages two I pieces and two J pieces (a
+  // diagonal tile stages the same rows into both blocks: no branch)
+  TileCtx<FORM> x(tid);
+  const int nI = I * BT + 16 * x.sr.seg, nJ = J * BT + 16 * x.sr.seg;
+  // the lane's load offsets; fast loads of inputs past N (edge tiles,
+  // N % 16 == 0) read a valid row instead: their LDS rows only reach
+  // baselines past N, never written
+  x.lds = lds;
+  x.row_stride = row_stride;
+  x.offI = (uint32_t)x.sr.rI * (uint32_t)row_stride + (uint32_t)(nI < N ? nI : 0);
+  x.offJ = (uint32_t)x.sr.rJ * (uint32_t)row_stride + (uint32_t)(nJ < N ? nJ : 0);
+  x.lane_rd = lane_read_offset<FORM>(lane);
+  x.rowA = 64 * wr;
+  x.rowB = 64 * wc;
+  x.sm = TileSums{0u, 0u, 0u, 0u};
+  // clear this thread's sums slot (it alone adds to it; a wave's LDS
+  // operations complete in order, and the previous tile ended on a barrier)
+  *reinterpret_cast<v4i*>(sum_slot(lds)) = v4i{0, 0, 0, 0};
+  typedef typename Acc<FORM>::T V;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      x.re[p][q] = V{};
+      x.im[p][q] = V{};
+    }
+
+  // samples integrated, padding of ragged chunks included; one dispatch on
+  // the wave's role per tile (a dispatch inside a loop over ranges, or a loop
+  // around one, costs the compiler many registers)
+  int teff;
+#define XENG_RANGES(C, A, B) \
+  tile_ranges<FORM, ALIGNED, DEEP, C, A, B>(x, samples, N, f, nI, nJ, rg, lds)
+  if (mask) {
+    switch (wave) {
+      case 0: teff = XENG_RANGES(true, 0, 0); break;
+      case 1: teff = XENG_RANGES(true, 1, 0); break;
+      case 2: teff = XENG_RANGES(true, 0, 1); break;
+      default: teff = XENG_RANGES(true, 1, 1); break;
+    }
+  } else {
+    switch (wave) {
+      case 0: teff = XENG_RANGES(false, 0, 0); break;
+      case 1: teff = XENG_RANGES(false, 1, 0); break;
+      case 2: teff = XENG_RANGES(false, 0, 1); break;
+      default: teff = XENG_RANGES(false, 1, 1); break;
+    }
+  }
+#undef XENG_RANGES
 
   // Per-input sums -> offset corrections, exchanged through the second
   // stage's LDS (free now; the sums slots lie in the first stage):
   // part[half][side][plane][128] holds each lane's partial sums, corr the row
   // (side 0) and column (side 1) corrections.
+  if (!Ranges::kSingle && rg.count() == 0)
+    __syncthreads();  // every sums slot is cleared before it is read
   int* part = reinterpret_cast<int*>(lds + STAGE_LDS);
   int2* corr = reinterpret_cast<int2*>(lds + STAGE_LDS + 2 * 2 * 2 * BT * 4);
   {
@@ -628,7 +683,7 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     const int side = tid >> 7, n = tid & (BT - 1);
     const int sr = part[((0 * 2 + side) * 2 + 0) * BT + n] + part[((1 * 2 + side) * 2 + 0) * BT + n];
     const int sm = part[((0 * 2 + side) * 2 + 1) * BT + n] + part[((1 * 2 + side) * 2 + 1) * BT + n];
-    const Corr cr = side == 0 ? row_corr<FORM>(sr, sm, nchunks * KC) : col_corr(sr, sm);
+    const Corr cr = side == 0 ? row_corr<FORM>(sr, sm, teff) : col_corr(sr, sm);
     corr[side * BT + n] = make_int2(cr.re, cr.im);
   }
   __syncthreads();
@@ -668,8 +723,31 @@ __global__ void __launch_bounds__(NTHREADS, 2) xcorr_tile_kernel(TileArgs a) {
   int I, J;
   tile_of(p, a.nt, I, J);
   const long long NB = (long long)a.N * (a.N + 1) / 2;
-  tile_body<FORM, ALIGNED, true>(a.samples, a.vis, a.N, a.row_stride, NB, f, I, J, t_begin,
-                                 t_end, mode, lds);
+  tile_body<FORM, ALIGNED, true>(a.samples, a.vis, a.N, a.row_stride, NB, f, I, J,
+                                 OneRange{t_begin, t_end}, mode, lds);
+}
+
+// Output gating (Sec. IV-C, "Output Gating"): the output is partitioned into
+// G sub-buffers by the time of each sample.  One workgroup per (channel,
+// tile, gate) integrates all runs of its gate, carrying its accumulators and
+// sums across runs, and writes its tile once: the samples are read once in
+// all and no atomic is needed, however many runs a gate has.  Consecutive
+// logical ids are the tiles of one (gate, channel), which share samples.
+template <int FORM, bool ALIGNED>
+__global__ void __launch_bounds__(NTHREADS, 2) xcorr_gated_kernel(GatedArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
+  const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
+  const int p = logical % a.tiles_per_chan;
+  const int rest = logical / a.tiles_per_chan;
+  const int f = rest % a.F;
+  const int g = rest / a.F;
+  int I, J;
+  tile_of(p, a.nt, I, J);
+  const long long NB = (long long)a.N * (a.N + 1) / 2;
+  const int r0 = a.gate_off[g], r1 = a.gate_off[g + 1];
+  tile_body<FORM, ALIGNED, false>(a.samples, a.vis + (long long)g * a.F * NB * 2, a.N,
+                                  a.row_stride, NB, f, I, J, RunList{a.runs + r0, r1 - r0},
+                                  a.write_mode, lds);
 }
 
 // Persistent batched kernel: every workgroup takes work items from a global
@@ -695,11 +773,11 @@ __global__ void __launch_bounds__(NTHREADS, 2)
     const long long NB = (long long)in.N * (in.N + 1) / 2;
     const long long stride = (long long)in.F * in.N;
     if (in.aligned)
-      tile_body<FORM, true, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J, it.t0,
-                                   it.t1, it.mode, lds);
+      tile_body<FORM, true, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J,
+                                   OneRange{it.t0, it.t1}, it.mode, lds);
     else
       tile_body<FORM, false, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J,
-                                    it.t0, it.t1, it.mode, lds);
+                                    OneRange{it.t0, it.t1}, it.mode, lds);
   }
 }
 
@@ -1117,6 +1195,25 @@ hipError_t launch_wide(const TileArgs& a, int form, hipStream_t stream) {
     hipLaunchKernelGGL((xcorr_wide_kernel<FORM_I8>), g, b, 0, stream, a);
   else
     hipLaunchKernelGGL((xcorr_wide_kernel<FORM_F8>), g, b, 0, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gated(const GatedArgs& a, int form, bool aligned, hipStream_t stream) {
+  const long long grid = (long long)a.F * a.tiles_per_chan * a.G;
+  if (grid <= 0) return hipSuccess;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 g((unsigned)grid), b(NTHREADS);
+  if (form == FORM_I8) {
+    if (aligned)
+      hipLaunchKernelGGL((xcorr_gated_kernel<FORM_I8, true>), g, b, 0, stream, a);
+    else
+      hipLaunchKernelGGL((xcorr_gated_kernel<FORM_I8, false>), g, b, 0, stream, a);
+  } else {
+    if (aligned)
+      hipLaunchKernelGGL((xcorr_gated_kernel<FORM_F8, true>), g, b, 0, stream, a);
+    else
+      hipLaunchKernelGGL((xcorr_gated_kernel<FORM_F8, false>), g, b, 0, stream, a);
+  }
   return hipGetLastError();
 }
 

@@ -51,6 +51,16 @@ struct xeng_plan_s {
   std::vector<const void*> uploaded;  // pointers now in d_insts
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t capture_stream = nullptr;
+
+  // output gating (xeng_plan_gated): run tables, pinned staging and device
+  int G_max = 0;
+  long long gate_off_cap = 0, runs_cap = 0;  // entries
+  int* h_gate_off = nullptr;
+  int2* h_runs = nullptr;
+  int* d_gate_off = nullptr;
+  int2* d_runs = nullptr;
+  hipEvent_t gate_done = nullptr;
+  bool gate_pending = false;
 };
 
 namespace {
@@ -124,6 +134,10 @@ int auto_slices(long long tiles, int T, int cu_count, int occupancy = kOccupancy
   return best;
 }
 
+// Samples one launch of the 128 x 128 kernels may integrate (sums of codes
+// stay exact: f32 below 2^24, int32 below 2^31).
+int segment_max(int form) { return form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : XENG_I8_SEG_MAX; }
+
 // Compute units of the current device for a plan being built; without a
 // device (plans can be built and validated on a host with no GPU) the count
 // of an MI355X.  Only the automatic slice count depends on it.
@@ -170,6 +184,35 @@ int xeng_plan(xeng_plan_t* out, int N, int F, int T_max, unsigned flags) {
   p->flags = flags;
   p->form = (int)(flags & XENG_FORM_MASK);
   p->accumulate = (flags & XENG_ACCUMULATE) != 0;
+  *out = p;
+  return XENG_OK;
+}
+
+int xeng_plan_gated(xeng_plan_t* out, int N, int F, int T_max, int G_max, unsigned flags) {
+  if (!out) return XENG_EINVAL;
+  *out = nullptr;
+  if (G_max < 1 || G_max > XENG_G_MAX) return XENG_EINVAL;
+  xeng_plan_t p = nullptr;
+  int rc = xeng_plan(&p, N, F, T_max, flags);
+  if (rc != XENG_OK) return rc;
+  const int seg = segment_max(p->form);
+  const long long nseg = (T_max + seg - 1) / seg;
+  p->G_max = G_max;
+  p->gate_off_cap = nseg * (G_max + 1);
+  p->runs_cap = (long long)T_max + nseg;  // at most one run per sample, plus a cut per segment
+  hipError_t e = hipHostMalloc((void**)&p->h_gate_off, p->gate_off_cap * sizeof(int),
+                               hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&p->h_runs, p->runs_cap * sizeof(int2), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_gate_off, p->gate_off_cap * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_runs, p->runs_cap * sizeof(int2));
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->gate_done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    rc = e == hipErrorOutOfMemory ? XENG_ENOMEM : XENG_EHIP;
+    (void)hipGetLastError();
+    xeng_destroy(p);
+    return rc;
+  }
   *out = p;
   return XENG_OK;
 }
@@ -273,6 +316,81 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
     }
     hipError_t e = wide ? xeng::launch_wide(a, p->form, s) : xeng::launch_tiles(a, p->form, aligned, s);
     if (e != hipSuccess) return hip_fail(p, e, "correlation kernel launch");
+  }
+  return XENG_OK;
+}
+
+int xeng_correlate_gated(xeng_plan_t p, const uint8_t* samples, int N, int F, int T,
+                         const int32_t* gate, int G, int32_t* vis, void* stream) {
+  if (!p || !samples || !gate || !vis || N < 1 || F < 1 || T < 1 || G < 1) return XENG_EINVAL;
+  if (p->kind != PLAN_SINGLE || p->G_max < 1 || G > p->G_max) return XENG_EPLAN;
+  if (T > XENG_T_EXACT_MAX) return XENG_EOVERFLOW;
+  if (N != p->N || F != p->F || T > p->T_max) return XENG_EPLAN;
+  int rc = ensure_cu_count(p);
+  if (rc != XENG_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (p->gate_pending) {
+    // the pinned staging may still be read by the previous call's copy
+    hipError_t e = hipEventSynchronize(p->gate_done);
+    if (e != hipSuccess) return hip_fail(p, e, "hipEventSynchronize");
+    p->gate_pending = false;
+  }
+  // Runs of equal gate per launch segment, grouped by gate in time order:
+  // segment k's gate g owns runs h_gate_off[k (G + 1) + g] .. [.. + g + 1].
+  const int seg = segment_max(p->form);
+  const int nseg = (T + seg - 1) / seg;
+  long long nruns = 0;
+  std::vector<int> count(G);
+  for (int k = 0; k < nseg; ++k) {
+    const int t0 = k * seg, t1 = std::min(T, t0 + seg);
+    std::fill(count.begin(), count.end(), 0);
+    for (int t = t0; t < t1;) {  // count the runs of each gate
+      const int g = gate[t];
+      int u = t + 1;
+      while (u < t1 && gate[u] == g) ++u;
+      if (g >= 0 && g < G) ++count[g];
+      t = u;
+    }
+    int* off = p->h_gate_off + (long long)k * (G + 1);
+    off[0] = (int)nruns;
+    for (int g = 0; g < G; ++g) off[g + 1] = off[g] + count[g];
+    std::vector<int> fill(off, off + G);
+    for (int t = t0; t < t1;) {  // and place them, in time order per gate
+      const int g = gate[t];
+      int u = t + 1;
+      while (u < t1 && gate[u] == g) ++u;
+      if (g >= 0 && g < G) p->h_runs[fill[g]++] = make_int2(t, u);
+      t = u;
+    }
+    nruns = off[G];
+  }
+  hipError_t e = hipSuccess;
+  if (nruns > 0)
+    e = hipMemcpyAsync(p->d_runs, p->h_runs, nruns * sizeof(int2), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->d_gate_off, p->h_gate_off, (size_t)nseg * (G + 1) * sizeof(int),
+                       hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(p->gate_done, s);
+  if (e != hipSuccess) return hip_fail(p, e, "gate table upload");
+  p->gate_pending = true;
+
+  const bool aligned = (N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples) & 15) == 0) &&
+                       ((long long)F * N <= (1LL << 25));
+  for (int k = 0; k < nseg; ++k) {
+    xeng::GatedArgs a;
+    a.samples = samples;
+    a.vis = vis;
+    a.N = N;
+    a.F = F;
+    a.G = G;
+    a.nt = (N + kTile - 1) / kTile;
+    a.tiles_per_chan = (int)tiles_per_channel(N);
+    a.write_mode = (p->accumulate || k > 0) ? xeng::WM_ADD : xeng::WM_STORE;
+    a.gate_off = p->d_gate_off + (long long)k * (G + 1);
+    a.runs = p->d_runs;
+    a.row_stride = (long long)F * N;
+    e = xeng::launch_gated(a, p->form, aligned, s);
+    if (e != hipSuccess) return hip_fail(p, e, "gated correlation kernel launch");
   }
   return XENG_OK;
 }
@@ -499,6 +617,11 @@ int xeng_destroy(xeng_plan_t p) {
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_counter) (void)hipFree(p->d_counter);
   if (p->h_insts) (void)hipHostFree(p->h_insts);
+  if (p->gate_done) (void)hipEventDestroy(p->gate_done);
+  if (p->d_gate_off) (void)hipFree(p->d_gate_off);
+  if (p->d_runs) (void)hipFree(p->d_runs);
+  if (p->h_gate_off) (void)hipHostFree(p->h_gate_off);
+  if (p->h_runs) (void)hipHostFree(p->h_runs);
   delete p;
   return XENG_OK;
 }

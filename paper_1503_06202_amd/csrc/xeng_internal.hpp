@@ -33,6 +33,22 @@ struct TileArgs {
 };
 
 hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t stream);
+
+// Output gating: every (channel, tile, gate) integrates the runs of its gate,
+// runs[gate_off[g] .. gate_off[g + 1]) (absolute [begin, end) sample ranges),
+// into vis + g * F * N(N+1) (gate-major output [G][F][N(N+1)/2][2]).
+struct GatedArgs {
+  const uint8_t* samples;
+  int32_t* vis;
+  int N, F, G;
+  int nt, tiles_per_chan;
+  int write_mode;         // WM_STORE or WM_ADD (one work item per output tile)
+  const int* gate_off;    // device [G + 1]
+  const int2* runs;       // device [gate_off[G]]
+  long long row_stride;
+};
+
+hipError_t launch_gated(const GatedArgs& a, int form, bool aligned, hipStream_t stream);
 // Clear the visibilities of tiles [first, first + count) (numbered as in
 // TileArgs) before their slices add into them.
 hipError_t launch_zero_tiles(int32_t* vis, int N, int tiles_per_chan, int nt, int first, int count,

@@ -60,18 +60,25 @@ class Plan:
 
     ``form`` is "i8" (int8 MFMA, int32 accumulators) or "f8" (FP8 e4m3 MFMA,
     f32 partial sums flushed to int32 every <= 32768 samples).  With
-    ``accumulate`` the frame's sums are added to ``vis``.
+    ``accumulate`` the frame's sums are added to ``vis``.  With ``gates`` > 0
+    the plan can also gate the output into up to that many buffers
+    (``correlate_gated``).
     """
 
     def __init__(self, N: int, F: int, T_max: int, form: str = "i8", accumulate: bool = False,
-                 split_t: int = 0, kernel: int = 0):
+                 split_t: int = 0, kernel: int = 0, gates: int = 0):
         if form not in FORMS:
             raise ValueError(f"form must be one of {sorted(FORMS)}")
         self.N, self.F, self.T_max, self.form, self.accumulate = N, F, T_max, form, accumulate
+        self.gates = gates
         flags = FORMS[form] | (_lib.XENG_ACCUMULATE if accumulate else 0)
         h = ctypes.c_void_p()
-        _lib.check(_lib.lib().xeng_plan(ctypes.byref(h), int(N), int(F), int(T_max), flags),
-                   "xeng_plan")
+        if gates:
+            _lib.check(_lib.lib().xeng_plan_gated(ctypes.byref(h), int(N), int(F), int(T_max),
+                                                  int(gates), flags), "xeng_plan_gated")
+        else:
+            _lib.check(_lib.lib().xeng_plan(ctypes.byref(h), int(N), int(F), int(T_max), flags),
+                       "xeng_plan")
         self._h = h
         if split_t or kernel:
             self.set_tuning(split_t, kernel)
@@ -99,6 +106,32 @@ class Plan:
         rc = _lib.lib().xeng_correlate(self._h, samples.data_ptr(), N, F, T, vis.data_ptr(),
                                        _stream_handle(stream))
         _lib.check(rc, "xeng_correlate", self._h.value)
+        return vis
+
+    def correlate_gated(self, samples: torch.Tensor, gate, G: int,
+                        vis: Optional[torch.Tensor] = None,
+                        stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """Gated visibilities [G][F][B][2]: ``gate`` (host, one int per sample)
+        picks each sample's buffer; values outside 0..G-1 drop the sample."""
+        import numpy as np
+
+        T, F, N = _check_samples(samples)
+        g = np.ascontiguousarray(np.asarray(gate, dtype=np.int32))
+        if g.shape != (T,):
+            raise ValueError("gate must hold one int per time sample")
+        shape = (int(G),) + vis_shape(N, F)
+        if vis is None:
+            if self.accumulate:
+                raise ValueError("an accumulating plan needs the vis to add into")
+            vis = torch.empty(shape, dtype=torch.int32, device=samples.device)
+        elif (vis.dtype != torch.int32 or tuple(vis.shape) != shape or not vis.is_cuda
+              or not vis.is_contiguous() or vis.device != samples.device):
+            raise ValueError(f"vis must be a contiguous int32 {shape} tensor on the samples' GPU")
+        rc = _lib.lib().xeng_correlate_gated(
+            self._h, samples.data_ptr(), N, F, T,
+            g.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(G), vis.data_ptr(),
+            _stream_handle(stream))
+        _lib.check(rc, "xeng_correlate_gated", self._h.value)
         return vis
 
     def close(self) -> None:

@@ -83,6 +83,29 @@ def test_correlate_validation_needs_no_gpu(L):
         L.xeng_destroy(h)
 
 
+def test_gated_validation_needs_no_gpu(L):
+    h = ctypes.c_void_p()
+    # gate-count and shape errors are found before any allocation
+    assert L.xeng_plan_gated(None, 64, 2, 1000, 4, 0) == _lib.XENG_EINVAL
+    assert L.xeng_plan_gated(ctypes.byref(h), 64, 2, 1000, 0, 0) == _lib.XENG_EINVAL
+    assert L.xeng_plan_gated(ctypes.byref(h), 64, 2, 1000, _lib.XENG_G_MAX + 1, 0) == _lib.XENG_EINVAL
+    assert L.xeng_plan_gated(ctypes.byref(h), 0, 2, 1000, 4, 0) == _lib.XENG_EINVAL
+    assert L.xeng_plan_gated(ctypes.byref(h), 64, 2, 1 << 24, 4, 0) == _lib.XENG_EOVERFLOW
+    assert not h.value
+    rc, hp = _plan(L, 64, 2, 1000)
+    assert rc == 0
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced
+    gate = (ctypes.c_int32 * 10)()
+    try:
+        assert L.xeng_correlate_gated(None, dummy, 64, 2, 10, gate, 2, dummy, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate_gated(hp, dummy, 64, 2, 10, None, 2, dummy, None) == _lib.XENG_EINVAL
+        assert L.xeng_correlate_gated(hp, dummy, 64, 2, 10, gate, 0, dummy, None) == _lib.XENG_EINVAL
+        # a plan made by xeng_plan cannot gate
+        assert L.xeng_correlate_gated(hp, dummy, 64, 2, 10, gate, 2, dummy, None) == _lib.XENG_EPLAN
+    finally:
+        L.xeng_destroy(hp)
+
+
 def test_batch_validation_needs_no_gpu(L):
     def plan(descs, flags=0):
         arr = (_lib.XengInstance * len(descs))(*[_lib.XengInstance(*d) for d in descs])
