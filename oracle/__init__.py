@@ -50,6 +50,9 @@ def load(mutant: Optional[str] = None, path: Optional[str] = None) -> ctypes.CDL
     lib.oracle_correlate_pairs.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip, ip,
                                            ctypes.c_int, i64p]
     lib.oracle_correlate_pairs.restype = ctypes.c_int
+    lib.oracle_correlate_shifted.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, ip, ctypes.POINTER(ctypes.c_int64)]
+    lib.oracle_correlate_shifted.restype = ctypes.c_int
     lib.oracle_threads.restype = ctypes.c_int
     _LIBS[key] = lib
     return lib
@@ -104,6 +107,28 @@ def correlate_gated(samples: np.ndarray, gate: np.ndarray, G: int,
         out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     if rc != 0:
         raise ValueError(f"oracle_correlate_gated failed ({rc})")
+    return out
+
+
+def correlate_shifted(ext: np.ndarray, D_max: int, delays: np.ndarray,
+                      lib: Optional[ctypes.CDLL] = None) -> np.ndarray:
+    """Visibilities int64 [F][N(N+1)/2][2] of inputs delayed by ``delays`` samples.
+
+    ``ext`` is [D_max + T][F][N]: D_max samples of history, then the frame.
+    """
+    e = np.ascontiguousarray(ext, dtype=np.uint8)
+    TT, F, N = e.shape
+    T = TT - int(D_max)
+    d = np.ascontiguousarray(delays, dtype=np.int32)
+    if T < 0 or d.shape != (N,):
+        raise ValueError("ext must hold D_max + T rows and delays one entry per input")
+    out = np.zeros((F, N * (N + 1) // 2, 2), dtype=np.int64)
+    lib = lib or load()
+    rc = lib.oracle_correlate_shifted(e.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), N, F, T,
+                                      int(D_max), d.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise ValueError(f"oracle_correlate_shifted failed ({rc})")
     return out
 
 

@@ -13,6 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "xeng_oracle.c")
 MUTANTS = ("NIBBLE", "OFFSET", "INDEX", "CONJ", "DROP", "TLAST")
+SHIFT_MUTANTS = ("SHIFT",)  # planted mistakes of the time-shifted mode only
 
 
 def lib_path(mutant: str | None = None, outdir: str | None = None) -> str:
@@ -26,7 +27,7 @@ def build(mutant: str | None = None, outdir: str | None = None, quiet: bool = Tr
     cmd = [cc, "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11",
            "-Wall", "-Wextra", "-o", out + ".tmp", SRC]
     if mutant:
-        if mutant not in MUTANTS:
+        if mutant not in MUTANTS + SHIFT_MUTANTS:
             raise ValueError(f"unknown mutant {mutant}")
         cmd.insert(1, f"-DORACLE_MUTANT_{mutant}")
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -187,6 +187,48 @@ int oracle_correlate_gated(const uint8_t *samples, int N, int F, int T,
 }
 
 /*
+ * Time shifting (Sec. IV-C, "Time Shifting"): input i is delayed by delays[i]
+ * samples before it is correlated, x'_i(t) = x_i(t - delays[i]).  `ext` holds
+ * D_max samples of history followed by the T samples of the frame,
+ * [D_max + T][F][N], so frame time t is row D_max + t and a delayed sample
+ * reaches back at most D_max rows.  out: [F][N(N+1)/2][2] as above.
+ */
+int oracle_correlate_shifted(const uint8_t *ext, int N, int F, int T, int D_max,
+                             const int *delays, int64_t *out) {
+    if (!ext || !delays || !out || N < 1 || F < 1 || T < 0 || D_max < 0) return -1;
+    for (int i = 0; i < N; ++i)
+        if (delays[i] < 0 || delays[i] > D_max) return -1;
+    const int64_t nb = (int64_t)N * (N + 1) / 2;
+    memset(out, 0, sizeof(int64_t) * (size_t)(F * nb * 2));
+    for (int f = 0; f < F; ++f) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int i = 0; i < N; ++i) {
+            for (int j = i; j < N; ++j) {
+                int64_t re = 0, im = 0;
+                for (int t = 0; t < T; ++t) {
+#ifdef ORACLE_MUTANT_SHIFT
+                    /* planted mistake: the delay applied to the other input */
+                    const uint8_t si = ext[((int64_t)(D_max + t - delays[j]) * F + f) * N + i];
+                    const uint8_t sj = ext[((int64_t)(D_max + t - delays[i]) * F + f) * N + j];
+#else
+                    const uint8_t si = ext[((int64_t)(D_max + t - delays[i]) * F + f) * N + i];
+                    const uint8_t sj = ext[((int64_t)(D_max + t - delays[j]) * F + f) * N + j];
+#endif
+                    const int64_t a = nib_real(si), bi = nib_imag(si);
+                    const int64_t c = nib_real(sj), d = nib_imag(sj);
+                    re += a * c + bi * d;
+                    im += bi * c - a * d;
+                }
+                int64_t *o = out + ((int64_t)f * nb + tri_index(i, j, N)) * 2;
+                o[0] = re;
+                o[1] = im;
+            }
+        }
+    }
+    return 0;
+}
+
+/*
  * Selected baselines only: out[k] = V_{f[k]}[i[k]][j[k]] as (re, im), summed
  * over t in [0, T) straight from the sample bytes (the same definition as
  * above, one baseline at a time), for checking full-size frames at sampled

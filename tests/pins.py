@@ -226,6 +226,58 @@ def pin_int32_boundary(lib):
     assert 2147483520 <= np.iinfo(np.int32).max < 128 * (1 << 24)
 
 
+# ------------------------------------------------- time shifting (Sec. IV-C)
+def _shift_frame(seed, TT, F, N):
+    return np.random.default_rng(seed).integers(0, 256, (TT, F, N), dtype=np.uint8)
+
+
+def pin_shift_zero_and_uniform(lib):
+    """No delay is the plain correlation of the frame; one delay d for every
+    input is the plain correlation of the window that starts d rows earlier."""
+    D, T, F, N = 9, 40, 2, 7
+    ext = _shift_frame(71, D + T, F, N)
+    got = oracle.correlate_shifted(ext, D, np.zeros(N, np.int32), lib=lib)
+    assert np.array_equal(got, oracle.correlate(ext[D:], lib=lib))
+    for d in (1, 5, 9):
+        got = oracle.correlate_shifted(ext, D, np.full(N, d, np.int32), lib=lib)
+        assert np.array_equal(got, oracle.correlate(ext[D - d:D - d + T], lib=lib)), d
+
+
+def pin_shift_aligns_delayed_copy(lib):
+    """Input 1 carries input 0 late by k samples; delaying input 0 by k lines
+    them up, so V_01 becomes the real power of the common signal, and it is
+    complex (not aligned) without the delay."""
+    D, T, N, k = 12, 64, 3, 5
+    ext = _shift_frame(72, D + T, 1, N)
+    ext[k:, 0, 1] = ext[:-k, 0, 0]               # x1(r) = x0(r - k)
+    delays = np.array([k, 0, 3], np.int32)
+    got = oracle.correlate_shifted(ext, D, delays, lib=lib)
+    re = (ext[D - k:D - k + T, 0, 0] >> 4).astype(np.int64) - 8
+    im = (ext[D - k:D - k + T, 0, 0] & 15).astype(np.int64) - 8
+    power = int((re * re + im * im).sum())
+    b01 = oracle.tri_index(0, 1, N)
+    assert got[0, b01].tolist() == [power, 0]
+    assert got[0, oracle.tri_index(0, 0, N)].tolist() == [power, 0]
+    plain = oracle.correlate_shifted(ext, D, np.zeros(N, np.int32), lib=lib)
+    assert plain[0, b01, 1] != 0
+
+
+def pin_shift_numpy_complex(lib):
+    """Shift the complex samples with numpy indexing and form X X^H (exact)."""
+    D, T, F, N = 6, 33, 2, 5
+    ext = _shift_frame(73, D + T, F, N)
+    delays = np.array([0, 6, 2, 2, 5], np.int32)
+    x = _as_complex((ext >> 4).astype(np.int64) - 8, (ext & 15).astype(np.int64) - 8)
+    rows = D + np.arange(T)[:, None] - delays[None, :]            # [T][N]
+    xs = x[rows, :, np.arange(N)[None, :]]                        # [T][N][F]
+    xs = np.transpose(xs, (2, 1, 0))                              # [F][N][T]
+    full = np.einsum("fit,fjt->fij", xs, np.conj(xs))
+    got = oracle.correlate_shifted(ext, D, delays, lib=lib)
+    assert np.array_equal(got, _packed_from_full(np.rint(full.real) + 1j * np.rint(full.imag)))
+
+
+SHIFT_PINS = (pin_shift_zero_and_uniform, pin_shift_aligns_delayed_copy, pin_shift_numpy_complex)
+
 FAST_PINS = (pin_counts, pin_worked_example, pin_extremes, pin_constant, pin_single_tone,
              pin_two_tone, pin_gram_invariants, pin_time_additivity, pin_symmetries,
              pin_numpy_complex, pin_brute_force, pin_exhaustive_codes)

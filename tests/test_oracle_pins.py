@@ -12,6 +12,25 @@ def test_pin(pin, oracle_lib):
     pin(oracle_lib)
 
 
+@pytest.mark.parametrize("pin", pins.SHIFT_PINS, ids=lambda p: p.__name__)
+def test_shift_pin(pin, oracle_lib):
+    pin(oracle_lib)
+
+
+@pytest.mark.parametrize("mutant", obuild.SHIFT_MUTANTS + ("CONJ", "INDEX"))
+def test_planted_shift_mistake_is_caught(mutant, tmp_path):
+    """A copy of the oracle with a planted mistake fails at least one shift pin."""
+    path = obuild.build(mutant, outdir=str(tmp_path))
+    lib = oracle.load(path=path)
+    failed = []
+    for pin in pins.SHIFT_PINS:
+        try:
+            pin(lib)
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, f"mutant {mutant} passed every shift pin"
+
+
 @pytest.mark.parametrize("mutant", obuild.MUTANTS)
 def test_planted_mistake_is_caught(mutant, tmp_path):
     """A copy of the oracle with one planted mistake fails at least one pin."""
