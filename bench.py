@@ -48,9 +48,9 @@ def parse():
                          "count for scaling the HBM counters of a profiler run)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
-    ap.add_argument("--forms", default="f8,gated,batched,stream",
+    ap.add_argument("--forms", default="f8,gated,shifted,batched,stream",
                     help="other forms reported beside the headline line (comma list of f8, "
-                         "gated, batched, stream; empty for none)")
+                         "gated, shifted, batched, stream; empty for none)")
     ap.add_argument("--stream-frames", type=int, default=1000)
     return ap.parse_args()
 
@@ -99,6 +99,38 @@ def bench_gated(d, w, steps, torch, G=16, period=8192):
     return {"workload": w.name, "gates": G, "period_samples": period, "ms_per_frame": ms,
             "cmac_per_s": w.cmac / (ms / 1e3), "pct_int8_peak": 100.0 * 8.0 * w.cmac / (ms / 1e3) / 1e12 / PEAK_TOPS["i8"],
             "output_bytes": out_bytes}
+
+
+def bench_shifted(d, w, steps, torch, D_max=60000):
+    """Time shifting on the same frame, for two delay patterns: two stations
+    (inputs 0..1023 undelayed, 1024..2047 delayed 40000 samples, 102 ms) and
+    the worst case, a seeded delay of 0..D_max samples for every group of 16
+    inputs (D_max = 60000 is 154 ms at the 2.56 us sample period; the paper
+    corrects up to 168 ms).  History rows in front of the frame hold the code
+    of 0 + 0i here."""
+    import numpy as np
+
+    from paper_1503_06202_amd import Plan
+
+    rng = np.random.default_rng(12)
+    patterns = {
+        "two_stations": np.where(np.arange(w.N) < w.N // 2, 0, 40000).astype(np.int32),
+        "per_16_inputs": np.repeat(rng.integers(0, D_max + 1, (w.N + 15) // 16),
+                                   16)[:w.N].astype(np.int32),
+    }
+    ext = torch.full((D_max + w.T, w.F, w.N), 0x88, dtype=torch.uint8, device=d.device)
+    ext[D_max:].copy_(d)
+    frame = ext[D_max:]
+    vis = torch.empty(vis_shape_of(w), dtype=torch.int32, device=d.device)
+    out = {"workload": w.name, "D_max": D_max}
+    with Plan(w.N, w.F, w.T) as p:
+        for name, delays in patterns.items():
+            p.set_delays(delays, D_max)
+            ms = _time_calls(lambda: p.correlate(frame, vis), max(3, steps // 4), torch)
+            out[name] = {"ms_per_frame": ms, "cmac_per_s": w.cmac / (ms / 1e3),
+                         "pct_int8_peak": 100.0 * 8.0 * w.cmac / (ms / 1e3) / 1e12 / PEAK_TOPS["i8"]}
+    del ext
+    return out
 
 
 def vis_shape_of(w):
@@ -311,6 +343,9 @@ def main():
     if "gated" in forms:
         _log("bench: gated form")
         extra["gated"] = bench_gated(d, w, args.steps, torch)
+    if "shifted" in forms:
+        _log("bench: shifted form")
+        extra["shifted"] = bench_shifted(d, w, args.steps, torch)
     if "batched" in forms:
         _log("bench: batched form")
         extra["batched"] = bench_batched(max(3, args.steps // 4), torch)

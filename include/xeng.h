@@ -152,6 +152,26 @@ int xeng_plan_gated(xeng_plan_t *out, int N, int F, int T_max, int G_max, unsign
 int xeng_correlate_gated(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
                          const int32_t *gate, int G, int32_t *vis, void *stream);
 
+/*
+ * Time shifting (Sec. IV-C, "Time Shifting"): inputs from distant stations
+ * decorrelate unless their samples are shifted in time.  After this call the
+ * plan's correlations (xeng_correlate and xeng_correlate_gated) read input n
+ * at time t - delays[n]:
+ *   V_f[i][j] = sum_t x[t - d_i][f][i] conj(x[t - d_j][f][j]),
+ * where rows t < 0 are the D_max rows of history the caller keeps in memory
+ * directly before `samples` (e.g. the previous frame's tail in a ring of
+ * frames); they must be readable, and they are read only for d > t.
+ *   delays  HOST array of N ints in 0..D_max, one value per aligned group of
+ *           16 inputs (the unit the kernels load); NULL turns shifting off.
+ * Needs (D_max + 64) F N < 2^31.  The delays are copied (synchronously) to
+ * plan-owned device memory.  The 128 x 256 tile kernel is not used while
+ * shifting.
+ * Errors: XENG_EINVAL (NULL plan, a delay outside 0..D_max, delays that differ
+ * within a 16-input group, D_max too large), XENG_EPLAN (batch plan),
+ * XENG_ENOMEM, XENG_EHIP.
+ */
+int xeng_plan_set_delays(xeng_plan_t p, const int32_t *delays, int D_max);
+
 /* Free a plan (NULL is accepted).  Waits for nothing: the caller must not
  * destroy a plan with work still in flight on its stream. */
 int xeng_destroy(xeng_plan_t p);

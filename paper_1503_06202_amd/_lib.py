@@ -33,6 +33,7 @@ EXPORTS = (
     "xeng_version", "xeng_strerror", "xeng_plan", "xeng_correlate", "xeng_plan_set_tuning",
     "xeng_destroy", "xeng_plan_error", "xeng_plan_batch", "xeng_correlate_batch",
     "xeng_correlate_batch_graph", "xeng_plan_gated", "xeng_correlate_gated",
+    "xeng_plan_set_delays",
 )
 
 
@@ -81,6 +82,8 @@ def lib() -> ctypes.CDLL:
     L.xeng_correlate_gated.argtypes = [vp, vp, ci, ci, ci, ctypes.POINTER(ctypes.c_int32), ci,
                                        vp, vp]
     L.xeng_correlate_gated.restype = ci
+    L.xeng_plan_set_delays.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ci]
+    L.xeng_plan_set_delays.restype = ci
     _lib = L
     return L
 

@@ -37,27 +37,35 @@ struct StageRole {
 // piece into the scalar offset, so that a thread keeps two 32-bit offsets
 // instead of 64-bit addresses.  The host keeps F N <= 2^25 on this path, so
 // every offset (at most 64 rows of F N bytes) stays below 2^31.
+//
+// Time shifting: the I and J pieces are read `shiftI` / `shiftJ` bytes (the
+// largest delay of the block, in rows) before `rows`, and a lane's offset
+// adds back its own segment's rows (see tile_body).
 __device__ __forceinline__ void load_pieces_fast(v4i (&raw)[4], const uint8_t* __restrict__ rows,
                                                  long long row_stride, uint32_t offI,
-                                                 uint32_t offJ) {
-  const __amdgpu_buffer_rsrc_t r =
-      __builtin_amdgcn_make_buffer_rsrc((void*)rows, (short)0, 0x7fffffff, 0x00020000);
+                                                 uint32_t offJ, long long shiftI = 0,
+                                                 long long shiftJ = 0) {
+  const __amdgpu_buffer_rsrc_t rI =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(rows - shiftI), (short)0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rJ =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(rows - shiftJ), (short)0, 0x7fffffff, 0x00020000);
   const int s16 = (int)(16 * row_stride);
-  raw[0] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(r, (int)offI, 0, 0));
-  raw[1] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(r, (int)offI, s16, 0));
-  raw[2] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(r, (int)offJ, 0, 0));
-  raw[3] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(r, (int)offJ, s16, 0));
+  raw[0] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rI, (int)offI, 0, 0));
+  raw[1] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rI, (int)offI, s16, 0));
+  raw[2] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rJ, (int)offJ, 0, 0));
+  raw[3] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rJ, (int)offJ, s16, 0));
 }
 
 // General path (frame edges, unaligned rows, ragged tails): byte loads of the
-// piece at time t, inputs n_first..n_first+15; absent samples and inputs read
-// as the code of 0 + 0i.
+// piece at time t, inputs n_first..n_first+15, delayed by d samples (row
+// t - d, which may lie in the history before the frame); absent samples and
+// inputs read as the code of 0 + 0i.
 __device__ __forceinline__ v4i load_piece_edge(const uint8_t* __restrict__ samples,
                                                long long row_stride, int f, int N, int n_first,
-                                               int t, int t_end) {
+                                               int t, int t_end, int d = 0) {
   uint32_t w[4] = {0x88888888u, 0x88888888u, 0x88888888u, 0x88888888u};
   if (t < t_end) {
-    const uint8_t* p = samples + (long long)t * row_stride + (long long)f * N + n_first;
+    const uint8_t* p = samples + (long long)(t - d) * row_stride + (long long)f * N + n_first;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
       if (n_first + e < N) {
@@ -74,11 +82,11 @@ __device__ __forceinline__ v4i load_piece_edge(const uint8_t* __restrict__ sampl
 __device__ __forceinline__ void load_pieces_edge(v4i (&raw)[4], const uint8_t* __restrict__ samples,
                                                  long long row_stride, int f, int N, int nI,
                                                  int nJ, const StageRole& sr, int t_chunk,
-                                                 int t_end) {
-  raw[0] = load_piece_edge(samples, row_stride, f, N, nI, t_chunk + sr.rI, t_end);
-  raw[1] = load_piece_edge(samples, row_stride, f, N, nI, t_chunk + sr.rI + 16, t_end);
-  raw[2] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ, t_end);
-  raw[3] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ + 16, t_end);
+                                                 int t_end, int dI = 0, int dJ = 0) {
+  raw[0] = load_piece_edge(samples, row_stride, f, N, nI, t_chunk + sr.rI, t_end, dI);
+  raw[1] = load_piece_edge(samples, row_stride, f, N, nI, t_chunk + sr.rI + 16, t_end, dI);
+  raw[2] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ, t_end, dJ);
+  raw[3] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ + 16, t_end, dJ);
 }
 
 // Split the nibbles of a piece and store them, unchanged, into the real and
@@ -406,6 +414,8 @@ struct TileCtx {
   const uint8_t* rows;  // channel's rows at the tile's first sample (uniform)
   long long row_stride;
   uint32_t offI, offJ;  // this thread's loads: its first I / J row and its inputs
+  long long shiftI, shiftJ;  // time shifting: block delays in bytes (uniform)
+  int dI, dJ;                // time shifting: this thread's segment delays (rows)
   StageRole sr;
   int lane_rd, rowA, rowB;
   typename Acc<FORM>::T re[2][2], im[2][2];
@@ -421,7 +431,7 @@ template <int FORM, bool COMPUTE, int SA, int SB>
 __device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, const v4i (&stg)[4],
                                             v4i (&ld)[4], int ld_chunk) {
   load_pieces_fast(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride, x.offI,
-                   x.offJ);
+                   x.offJ, x.shiftI, x.shiftJ);
   // keep the loads at the top of the step: they have a whole step to land
   __builtin_amdgcn_sched_barrier(0);
   compute_chunk<FORM, COMPUTE, true, SA, SB>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im,
@@ -439,9 +449,10 @@ template <int FORM, bool COMPUTE, int SA, int SB>
 __device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int nfast) {
   constexpr int B0 = 0, B1 = STAGE_LDS;
   v4i rawA[4], rawB[4];
-  load_pieces_fast(rawA, x.rows, x.row_stride, x.offI, x.offJ);
+  load_pieces_fast(rawA, x.rows, x.row_stride, x.offI, x.offJ, x.shiftI, x.shiftJ);
   stage_pieces(rawA, x.lds + B0, x.sr);
-  load_pieces_fast(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.offI, x.offJ);
+  load_pieces_fast(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.offI, x.offJ,
+                   x.shiftI, x.shiftJ);
   __syncthreads();
   for (int c = 0; c < nsteady; c += 2) {
     steady_step<FORM, COMPUTE, SA, SB>(x, B0, B1, rawA, rawB, min(c + 2, nfast - 1));
@@ -457,7 +468,7 @@ template <int FORM, bool COMPUTE, int SA, int SB>
 __device__ __forceinline__ void steady_step1(TileCtx<FORM>& x, int cur, int nxt, v4i (&raw)[4],
                                              int ld_chunk) {
   load_pieces_fast(raw, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride, x.offI,
-                   x.offJ);
+                   x.offJ, x.shiftI, x.shiftJ);
   __builtin_amdgcn_sched_barrier(0);
   compute_chunk<FORM, COMPUTE, false, SA, SB>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im,
                                               x.sm);
@@ -470,7 +481,7 @@ template <int FORM, bool COMPUTE, int SA, int SB>
 __device__ __forceinline__ void steady_chunks1(TileCtx<FORM>& x, int nsteady, int nfast) {
   constexpr int B0 = 0, B1 = STAGE_LDS;
   v4i raw[4];
-  load_pieces_fast(raw, x.rows, x.row_stride, x.offI, x.offJ);
+  load_pieces_fast(raw, x.rows, x.row_stride, x.offI, x.offJ, x.shiftI, x.shiftJ);
   stage_pieces(raw, x.lds + B0, x.sr);
   __syncthreads();
   for (int c = 0; c < nsteady; c += 2) {
@@ -536,9 +547,11 @@ __device__ __forceinline__ int tile_range(TileCtx<FORM>& x, const uint8_t* __res
   v4i raw[4];
   auto load = [&](int cc) {
     if (ALIGNED && (cc + 1) * KC <= len)
-      load_pieces_fast(raw, rows + (long long)cc * KC * row_stride, row_stride, x.offI, x.offJ);
+      load_pieces_fast(raw, rows + (long long)cc * KC * row_stride, row_stride, x.offI, x.offJ,
+                       x.shiftI, x.shiftJ);
     else
-      load_pieces_edge(raw, samples, row_stride, f, N, nI, nJ, x.sr, t_begin + cc * KC, t_end);
+      load_pieces_edge(raw, samples, row_stride, f, N, nI, nJ, x.sr, t_begin + cc * KC, t_end,
+                       x.dI, x.dJ);
   };
   if (c < nchunks) {
     load(c);
@@ -589,11 +602,19 @@ __device__ __forceinline__ int tile_ranges(TileCtx<FORM>& x, const uint8_t* __re
 // Wave (wr, wc) sums A fragment wc and B fragment wr (see TileSums).  The
 // fragment choice is a compile-time parameter of the chunk loops, dispatched
 // once per tile on the wave index, so that the loops stay straight-line code.
-template <int FORM, bool ALIGNED, bool DEEP, class Ranges>
+//
+// Time shifting (Sec. IV-C, "Time Shifting"): with seg_delay (delays per
+// 16-input segment, in samples) and blk_delay (their maximum per 128-input
+// block), input n is read at time t - delay(n); rows before the frame come
+// from the history the caller keeps in front of `samples`.  A block's largest
+// delay moves its (scalar) load base back; a lane's offset adds back the rows
+// its own segment is delayed less.  NULL tables: no shift.
+template <int FORM, bool ALIGNED, bool DEEP, bool SHIFT, class Ranges>
 __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, int32_t* vis,
                                           int N, long long row_stride, long long NB, int f,
                                           int I, int J, const Ranges& rg, int mode,
-                                          uint8_t* lds) {
+                                          uint8_t* lds, const int* seg_delay = nullptr,
+                                          const int* blk_delay = nullptr) {
   // the wave index is uniform per wave: read it into a scalar register so that
   // every branch on it is a uniform one
   const int tid = threadIdx.x, lane = tid & 63;
@@ -620,8 +641,18 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   // baselines past N, never written
   x.lds = lds;
   x.row_stride = row_stride;
-  x.offI = (uint32_t)x.sr.rI * (uint32_t)row_stride + (uint32_t)(nI < N ? nI : 0);
-  x.offJ = (uint32_t)x.sr.rJ * (uint32_t)row_stride + (uint32_t)(nJ < N ? nJ : 0);
+  int DI = 0, DJ = 0;
+  x.dI = x.dJ = 0;
+  if (SHIFT) {
+    DI = blk_delay[I];
+    DJ = blk_delay[J];
+    x.dI = nI < N ? seg_delay[nI >> 4] : DI;
+    x.dJ = nJ < N ? seg_delay[nJ >> 4] : DJ;
+  }
+  x.shiftI = (long long)DI * row_stride;
+  x.shiftJ = (long long)DJ * row_stride;
+  x.offI = (uint32_t)(x.sr.rI + DI - x.dI) * (uint32_t)row_stride + (uint32_t)(nI < N ? nI : 0);
+  x.offJ = (uint32_t)(x.sr.rJ + DJ - x.dJ) * (uint32_t)row_stride + (uint32_t)(nJ < N ? nJ : 0);
   x.lane_rd = lane_read_offset<FORM>(lane);
   x.rowA = 64 * wr;
   x.rowB = 64 * wc;
@@ -692,7 +723,7 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   __syncthreads();  // the corrections are read before the LDS is reused
 }
 
-template <int FORM, bool ALIGNED>
+template <int FORM, bool ALIGNED, bool SHIFT>
 __global__ void __launch_bounds__(NTHREADS, 2) xcorr_tile_kernel(TileArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
   // Head items first (the dispatcher issues workgroups in order), then the
@@ -723,8 +754,10 @@ __global__ void __launch_bounds__(NTHREADS, 2) xcorr_tile_kernel(TileArgs a) {
   int I, J;
   tile_of(p, a.nt, I, J);
   const long long NB = (long long)a.N * (a.N + 1) / 2;
-  tile_body<FORM, ALIGNED, true>(a.samples, a.vis, a.N, a.row_stride, NB, f, I, J,
-                                 OneRange{t_begin, t_end}, mode, lds);
+  // (shifted frames prefetch one chunk ahead: the shift costs registers)
+  tile_body<FORM, ALIGNED, !SHIFT, SHIFT>(a.samples, a.vis, a.N, a.row_stride, NB, f, I, J,
+                                        OneRange{t_begin, t_end}, mode, lds, a.seg_delay,
+                                        a.blk_delay);
 }
 
 // Output gating (Sec. IV-C, "Output Gating"): the output is partitioned into
@@ -733,7 +766,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) xcorr_tile_kernel(TileArgs a) {
 // sums across runs, and writes its tile once: the samples are read once in
 // all and no atomic is needed, however many runs a gate has.  Consecutive
 // logical ids are the tiles of one (gate, channel), which share samples.
-template <int FORM, bool ALIGNED>
+template <int FORM, bool ALIGNED, bool SHIFT>
 __global__ void __launch_bounds__(NTHREADS, 2) xcorr_gated_kernel(GatedArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
   const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
@@ -745,9 +778,10 @@ __global__ void __launch_bounds__(NTHREADS, 2) xcorr_gated_kernel(GatedArgs a) {
   tile_of(p, a.nt, I, J);
   const long long NB = (long long)a.N * (a.N + 1) / 2;
   const int r0 = a.gate_off[g], r1 = a.gate_off[g + 1];
-  tile_body<FORM, ALIGNED, false>(a.samples, a.vis + (long long)g * a.F * NB * 2, a.N,
-                                  a.row_stride, NB, f, I, J, RunList{a.runs + r0, r1 - r0},
-                                  a.write_mode, lds);
+  tile_body<FORM, ALIGNED, false, SHIFT>(a.samples, a.vis + (long long)g * a.F * NB * 2, a.N,
+                                         a.row_stride, NB, f, I, J,
+                                         RunList{a.runs + r0, r1 - r0}, a.write_mode, lds,
+                                         a.seg_delay, a.blk_delay);
 }
 
 // Persistent batched kernel: every workgroup takes work items from a global
@@ -773,10 +807,10 @@ __global__ void __launch_bounds__(NTHREADS, 2)
     const long long NB = (long long)in.N * (in.N + 1) / 2;
     const long long stride = (long long)in.F * in.N;
     if (in.aligned)
-      tile_body<FORM, true, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J,
+      tile_body<FORM, true, false, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J,
                                    OneRange{it.t0, it.t1}, it.mode, lds);
     else
-      tile_body<FORM, false, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J,
+      tile_body<FORM, false, false, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J,
                                     OneRange{it.t0, it.t1}, it.mode, lds);
   }
 }
@@ -1198,22 +1232,34 @@ hipError_t launch_wide(const TileArgs& a, int form, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// Launch K<FORM, ALIGNED, SHIFT> for the run-time form, alignment and shift.
+#define XENG_DISPATCH3(K, form, aligned, shift, g, b, stream, arg)                            \
+  do {                                                                                        \
+    if ((form) == FORM_I8) {                                                                  \
+      if (aligned) {                                                                          \
+        if (shift) hipLaunchKernelGGL((K<FORM_I8, true, true>), g, b, 0, stream, arg);        \
+        else hipLaunchKernelGGL((K<FORM_I8, true, false>), g, b, 0, stream, arg);             \
+      } else {                                                                                \
+        if (shift) hipLaunchKernelGGL((K<FORM_I8, false, true>), g, b, 0, stream, arg);       \
+        else hipLaunchKernelGGL((K<FORM_I8, false, false>), g, b, 0, stream, arg);            \
+      }                                                                                       \
+    } else {                                                                                  \
+      if (aligned) {                                                                          \
+        if (shift) hipLaunchKernelGGL((K<FORM_F8, true, true>), g, b, 0, stream, arg);        \
+        else hipLaunchKernelGGL((K<FORM_F8, true, false>), g, b, 0, stream, arg);             \
+      } else {                                                                                \
+        if (shift) hipLaunchKernelGGL((K<FORM_F8, false, true>), g, b, 0, stream, arg);       \
+        else hipLaunchKernelGGL((K<FORM_F8, false, false>), g, b, 0, stream, arg);            \
+      }                                                                                       \
+    }                                                                                         \
+  } while (0)
+
 hipError_t launch_gated(const GatedArgs& a, int form, bool aligned, hipStream_t stream) {
   const long long grid = (long long)a.F * a.tiles_per_chan * a.G;
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 g((unsigned)grid), b(NTHREADS);
-  if (form == FORM_I8) {
-    if (aligned)
-      hipLaunchKernelGGL((xcorr_gated_kernel<FORM_I8, true>), g, b, 0, stream, a);
-    else
-      hipLaunchKernelGGL((xcorr_gated_kernel<FORM_I8, false>), g, b, 0, stream, a);
-  } else {
-    if (aligned)
-      hipLaunchKernelGGL((xcorr_gated_kernel<FORM_F8, true>), g, b, 0, stream, a);
-    else
-      hipLaunchKernelGGL((xcorr_gated_kernel<FORM_F8, false>), g, b, 0, stream, a);
-  }
+  XENG_DISPATCH3(xcorr_gated_kernel, form, aligned, a.seg_delay != nullptr, g, b, stream, a);
   return hipGetLastError();
 }
 
@@ -1223,17 +1269,7 @@ hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t s
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 g((unsigned)grid), b(NTHREADS);
-  if (form == FORM_I8) {
-    if (aligned)
-      hipLaunchKernelGGL((xcorr_tile_kernel<FORM_I8, true>), g, b, 0, stream, a);
-    else
-      hipLaunchKernelGGL((xcorr_tile_kernel<FORM_I8, false>), g, b, 0, stream, a);
-  } else {
-    if (aligned)
-      hipLaunchKernelGGL((xcorr_tile_kernel<FORM_F8, true>), g, b, 0, stream, a);
-    else
-      hipLaunchKernelGGL((xcorr_tile_kernel<FORM_F8, false>), g, b, 0, stream, a);
-  }
+  XENG_DISPATCH3(xcorr_tile_kernel, form, aligned, a.seg_delay != nullptr, g, b, stream, a);
   return hipGetLastError();
 }
 

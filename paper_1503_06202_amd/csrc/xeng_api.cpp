@@ -61,6 +61,11 @@ struct xeng_plan_s {
   int2* d_runs = nullptr;
   hipEvent_t gate_done = nullptr;
   bool gate_pending = false;
+
+  // time shifting (xeng_plan_set_delays): per-segment delays and block maxima
+  bool shift = false;
+  int* d_seg_delay = nullptr;
+  int* d_blk_delay = nullptr;
 };
 
 namespace {
@@ -217,6 +222,36 @@ int xeng_plan_gated(xeng_plan_t* out, int N, int F, int T_max, int G_max, unsign
   return XENG_OK;
 }
 
+int xeng_plan_set_delays(xeng_plan_t p, const int32_t* delays, int D_max) {
+  if (!p) return XENG_EINVAL;
+  if (p->kind != PLAN_SINGLE) return XENG_EPLAN;
+  if (!delays) {
+    p->shift = false;
+    return XENG_OK;
+  }
+  const int N = p->N, nseg = (N + 15) / 16, nt = (N + kTile - 1) / kTile;
+  if (D_max < 0 || (long long)(D_max + 64) * p->F * N >= (1LL << 31)) return XENG_EINVAL;
+  std::vector<int> seg(nseg), blk(nt, 0);
+  for (int n = 0; n < N; ++n) {
+    if (delays[n] < 0 || delays[n] > D_max) return XENG_EINVAL;
+    if (delays[n] != delays[n & ~15]) return XENG_EINVAL;  // one delay per 16-input segment
+  }
+  for (int k = 0; k < nseg; ++k) {
+    seg[k] = delays[16 * k];
+    blk[(16 * k) / kTile] = std::max(blk[(16 * k) / kTile], seg[k]);
+  }
+  hipError_t e = hipSuccess;
+  if (!p->d_seg_delay) e = hipMalloc((void**)&p->d_seg_delay, nseg * sizeof(int));
+  if (e == hipSuccess && !p->d_blk_delay) e = hipMalloc((void**)&p->d_blk_delay, nt * sizeof(int));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_seg_delay, seg.data(), nseg * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_blk_delay, blk.data(), nt * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? XENG_ENOMEM : hip_fail(p, e, "delay upload");
+  p->shift = true;
+  return XENG_OK;
+}
+
 int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel) {
   if (!p || split_t < 0 || kernel < 0 || kernel > 2) return XENG_EINVAL;
   p->split_t = split_t;
@@ -242,7 +277,7 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
                        ((long long)F * N <= (1LL << 25));
   // wide tiles (128 x 256, one workgroup per CU) only on request and when
   // the rows allow fast loads; 128 x 128 (two workgroups per CU) otherwise
-  const bool wide = aligned && p->kernel == 2;
+  const bool wide = aligned && p->kernel == 2 && !p->shift;
   const long long tpc = wide ? wide_tiles_per_channel(N) : tiles_per_channel(N);
   const int occupancy = wide ? 1 : kOccupancy;
   // The FP8 form integrates at most XENG_F8_FLUSH_MAX samples per launch (f32
@@ -301,6 +336,8 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
     a.tail_slices = tail_slices;
     a.tail_len = tail_len;
     a.tail_mode = xeng::WM_ATOMIC;
+    a.seg_delay = p->shift ? p->d_seg_delay : nullptr;
+    a.blk_delay = p->shift ? p->d_blk_delay : nullptr;
     if (nslices > 1) {
       a.write_mode = xeng::WM_ATOMIC;
       if (!add) {
@@ -389,6 +426,8 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t* samples, int N, int F, in
     a.gate_off = p->d_gate_off + (long long)k * (G + 1);
     a.runs = p->d_runs;
     a.row_stride = (long long)F * N;
+    a.seg_delay = p->shift ? p->d_seg_delay : nullptr;
+    a.blk_delay = p->shift ? p->d_blk_delay : nullptr;
     e = xeng::launch_gated(a, p->form, aligned, s);
     if (e != hipSuccess) return hip_fail(p, e, "gated correlation kernel launch");
   }
@@ -622,6 +661,8 @@ int xeng_destroy(xeng_plan_t p) {
   if (p->d_runs) (void)hipFree(p->d_runs);
   if (p->h_gate_off) (void)hipHostFree(p->h_gate_off);
   if (p->h_runs) (void)hipHostFree(p->h_runs);
+  if (p->d_seg_delay) (void)hipFree(p->d_seg_delay);
+  if (p->d_blk_delay) (void)hipFree(p->d_blk_delay);
   delete p;
   return XENG_OK;
 }

@@ -30,6 +30,10 @@ struct TileArgs {
   int tail_slices;
   int tail_len;
   int tail_mode;
+  // time shifting: delays per 16-input segment and their maximum per
+  // 128-input block (device), or NULL
+  const int* seg_delay;
+  const int* blk_delay;
 };
 
 hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t stream);
@@ -46,6 +50,8 @@ struct GatedArgs {
   const int* gate_off;    // device [G + 1]
   const int2* runs;       // device [gate_off[G]]
   long long row_stride;
+  const int* seg_delay;   // time shifting, as in TileArgs
+  const int* blk_delay;
 };
 
 hipError_t launch_gated(const GatedArgs& a, int form, bool aligned, hipStream_t stream);

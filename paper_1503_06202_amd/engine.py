@@ -108,6 +108,23 @@ class Plan:
         _lib.check(rc, "xeng_correlate", self._h.value)
         return vis
 
+    def set_delays(self, delays, D_max: int = 0) -> None:
+        """Shift input n by delays[n] samples (one value per 16-input group;
+        None turns shifting off).  The D_max rows before each samples tensor
+        passed to this plan must hold the history: pass a view that starts
+        D_max rows into a buffer of [history; frame]."""
+        import numpy as np
+
+        if delays is None:
+            _lib.check(_lib.lib().xeng_plan_set_delays(self._h, None, 0), "xeng_plan_set_delays")
+            return
+        d = np.ascontiguousarray(np.asarray(delays, dtype=np.int32))
+        if d.shape != (self.N,):
+            raise ValueError("delays must hold one int per input")
+        _lib.check(_lib.lib().xeng_plan_set_delays(
+            self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(D_max)),
+            "xeng_plan_set_delays", self._h.value)
+
     def correlate_gated(self, samples: torch.Tensor, gate, G: int,
                         vis: Optional[torch.Tensor] = None,
                         stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:

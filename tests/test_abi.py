@@ -106,6 +106,30 @@ def test_gated_validation_needs_no_gpu(L):
         L.xeng_destroy(hp)
 
 
+def test_delay_validation_needs_no_gpu(L):
+    rc, h = _plan(L, 40, 2, 1000)
+    assert rc == 0
+    D = (ctypes.c_int32 * 40)
+    try:
+        ok = D(*([5] * 16 + [0] * 16 + [9] * 8))
+        assert L.xeng_plan_set_delays(None, ok, 10) == _lib.XENG_EINVAL
+        assert L.xeng_plan_set_delays(h, ok, 8) == _lib.XENG_EINVAL        # 9 > D_max
+        assert L.xeng_plan_set_delays(h, ok, -1) == _lib.XENG_EINVAL
+        split = D(*([5] * 15 + [6] + [0] * 24))                          # differs within a group
+        assert L.xeng_plan_set_delays(h, split, 10) == _lib.XENG_EINVAL
+        assert L.xeng_plan_set_delays(h, ok, 1 << 30) == _lib.XENG_EINVAL  # offsets past 2^31
+        assert L.xeng_plan_set_delays(h, None, 0) == _lib.XENG_OK           # off
+    finally:
+        L.xeng_destroy(h)
+    arr = (_lib.XengInstance * 1)(_lib.XengInstance(8, 1, 8, 0))
+    hb = ctypes.c_void_p()
+    assert L.xeng_plan_batch(ctypes.byref(hb), arr, 1, 0) == 0
+    try:
+        assert L.xeng_plan_set_delays(hb, D(*([0] * 40)), 0) == _lib.XENG_EPLAN
+    finally:
+        L.xeng_destroy(hb)
+
+
 def test_batch_validation_needs_no_gpu(L):
     def plan(descs, flags=0):
         arr = (_lib.XengInstance * len(descs))(*[_lib.XengInstance(*d) for d in descs])
