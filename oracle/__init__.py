@@ -13,7 +13,8 @@ Parity pins (see ``tests/test_oracle_pins.py``): a hand-worked example, closed
 forms for constant, single-tone and two-tone inputs, Gram-matrix invariants,
 numpy complex128 ``X @ X^H``, pure-Python brute force, the exhaustive 256 x 256
 code pairs and the int32 boundary.  The gated variant is pinned by summing its
-gates back to the ungated result and by brute force.
+gates back to the ungated result and by brute force; the shifted and flagged
+variants have pins of their own.
 """
 from __future__ import annotations
 
@@ -53,6 +54,9 @@ def load(mutant: Optional[str] = None, path: Optional[str] = None) -> ctypes.CDL
     lib.oracle_correlate_shifted.argtypes = [u8p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                              ctypes.c_int, ip, ctypes.POINTER(ctypes.c_int64)]
     lib.oracle_correlate_shifted.restype = ctypes.c_int
+    lib.oracle_correlate_flagged.argtypes = [u8p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int,
+                                             ctypes.c_int, ctypes.c_int, i64p, i64p]
+    lib.oracle_correlate_flagged.restype = ctypes.c_int
     lib.oracle_threads.restype = ctypes.c_int
     _LIBS[key] = lib
     return lib
@@ -130,6 +134,50 @@ def correlate_shifted(ext: np.ndarray, D_max: int, delays: np.ndarray,
     if rc != 0:
         raise ValueError(f"oracle_correlate_shifted failed ({rc})")
     return out
+
+
+def correlate_flagged(samples: np.ndarray, flags: np.ndarray,
+                      lib: Optional[ctypes.CDLL] = None):
+    """Visibilities and valid-pair counts of a frame with invalid samples.
+
+    ``flags`` is uint32 ``[T][F][ceil(N/32)]``, bit ``i % 32`` of word ``i // 32``
+    set when sample ``(t, f, i)`` is invalid.  Returns ``(vis, counts)``: int64
+    ``[F][N(N+1)/2][2]`` summed over the times where both inputs are valid, and
+    int64 ``[F][N(N+1)/2]``, the number of such times.
+    """
+    s = np.ascontiguousarray(samples, dtype=np.uint8)
+    T, F, N = s.shape
+    fl = np.ascontiguousarray(flags, dtype=np.uint32)
+    if fl.shape != (T, F, (N + 31) // 32):
+        raise ValueError("flags must be uint32 [T][F][ceil(N/32)]")
+    nb = N * (N + 1) // 2
+    out = np.zeros((F, nb, 2), dtype=np.int64)
+    counts = np.zeros((F, nb), dtype=np.int64)
+    lib = lib or load()
+    rc = lib.oracle_correlate_flagged(
+        s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+        fl.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), N, F, T,
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+        counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise ValueError(f"oracle_correlate_flagged failed ({rc})")
+    return out, counts
+
+
+def normalize(vis: np.ndarray, counts: np.ndarray, scale: float) -> np.ndarray:
+    """Renormalised visibilities, float32 ``[F][N(N+1)/2][2]``.
+
+    Each baseline's integrated sum is rescaled by the fraction of valid pairs:
+    ``V * scale / C`` in float64, rounded once to float32, and 0 where C == 0
+    (no valid pair).  With ``scale`` = the number of samples integrated this is
+    the sum the integration would have had with no data missing; with
+    ``scale`` = 1 it is the mean product per valid sample.
+    """
+    v = np.asarray(vis, dtype=np.float64)
+    c = np.asarray(counts, dtype=np.float64)[..., None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out = np.where(c > 0, v * float(scale) / c, 0.0)
+    return out.astype(np.float32)
 
 
 def correlate_pairs(samples: np.ndarray, f: np.ndarray, i: np.ndarray, j: np.ndarray,

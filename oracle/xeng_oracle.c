@@ -229,6 +229,58 @@ int oracle_correlate_shifted(const uint8_t *ext, int N, int F, int T, int D_max,
 }
 
 /*
+ * Flagged data (Sec. IV-A, "Data Flow"): lost packets and F-engine flags
+ * (ADC saturation, FFT overflow) mark samples as invalid, and the count of
+ * such data renormalises the integrated matrices.  A flagged sample takes no
+ * part in the integration, whatever its byte holds:
+ *
+ *     V_f[i][j] = sum over t with both samples valid of x_i conj(x_j),
+ *     C_f[i][j] = number of t with both x[t][f][i] and x[t][f][j] valid.
+ *
+ * flags: uint32 [T][F][W], W = ceil(N / 32); bit (i % 32) of word i / 32 set
+ * means sample (t, f, i) is invalid.  out: [F][N(N+1)/2][2] as above;
+ * counts: int64 [F][N(N+1)/2].
+ */
+static inline int flagged(const uint32_t *flags, int64_t t, int f, int i, int F, int W) {
+    return (int)((flags[(t * F + f) * W + (i >> 5)] >> (i & 31)) & 1u);
+}
+
+int oracle_correlate_flagged(const uint8_t *samples, const uint32_t *flags, int N, int F, int T,
+                             int64_t *out, int64_t *counts) {
+    if (!samples || !flags || !out || !counts || N < 1 || F < 1 || T < 0) return -1;
+    const int W = (N + 31) / 32;
+    const int64_t nb = (int64_t)N * (N + 1) / 2;
+    for (int f = 0; f < F; ++f) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int i = 0; i < N; ++i) {
+            for (int j = i; j < N; ++j) {
+                int64_t re = 0, im = 0, n = 0;
+                for (int t = 0; t < T; ++t) {
+#ifdef ORACLE_MUTANT_FLAG
+                    /* planted mistake: only the first input's flag is honoured */
+                    if (flagged(flags, t, f, i, F, W)) continue;
+#else
+                    if (flagged(flags, t, f, i, F, W) || flagged(flags, t, f, j, F, W)) continue;
+#endif
+                    const uint8_t si = samples[((int64_t)t * F + f) * N + i];
+                    const uint8_t sj = samples[((int64_t)t * F + f) * N + j];
+                    const int64_t a = nib_real(si), bi = nib_imag(si);
+                    const int64_t c = nib_real(sj), d = nib_imag(sj);
+                    re += a * c + bi * d;
+                    im += bi * c - a * d;
+                    ++n;
+                }
+                const int64_t b = (int64_t)f * nb + tri_index(i, j, N);
+                out[b * 2] = re;
+                out[b * 2 + 1] = im;
+                counts[b] = n;
+            }
+        }
+    }
+    return 0;
+}
+
+/*
  * Selected baselines only: out[k] = V_{f[k]}[i[k]][j[k]] as (re, im), summed
  * over t in [0, T) straight from the sample bytes (the same definition as
  * above, one baseline at a time), for checking full-size frames at sampled

@@ -19,3 +19,4 @@ from .frames import (  # noqa: F401
     stream_frame,
     workload,
 )
+from .flags import gen_flags, pack_flags, unpack_flags  # noqa: F401

@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 import oracle
-from synth import encode
+from synth import encode, pack_flags
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
@@ -277,6 +277,82 @@ def pin_shift_numpy_complex(lib):
 
 
 SHIFT_PINS = (pin_shift_zero_and_uniform, pin_shift_aligns_delayed_copy, pin_shift_numpy_complex)
+
+
+# ------------------------------------------- flagged data (Sec. IV-A, Data Flow)
+def _flag_frame(seed, T, F, N, p):
+    rng = np.random.default_rng(seed)
+    samples = rng.integers(0, 256, (T, F, N), dtype=np.uint8)
+    invalid = rng.random((T, F, N)) < p
+    return samples, invalid
+
+
+def pin_flag_none_and_all(lib):
+    """No flag gives the plain correlation and T valid pairs everywhere; every
+    sample flagged gives zero sums and zero counts, whatever the bytes hold."""
+    T, F, N = 37, 2, 35
+    samples, _ = _flag_frame(81, T, F, N, 0.0)
+    vis, cnt = oracle.correlate_flagged(samples, pack_flags(np.zeros((T, F, N), bool)), lib=lib)
+    assert np.array_equal(vis, oracle.correlate(samples, lib=lib))
+    assert (cnt == T).all()
+    vis, cnt = oracle.correlate_flagged(samples, pack_flags(np.ones((T, F, N), bool)), lib=lib)
+    assert not vis.any() and not cnt.any()
+
+
+def pin_flag_single_input(lib):
+    """Input k flagged at a set S of times: every baseline that involves k has
+    T - |S| valid pairs, every other one T, and V equals the correlation of
+    the frame with k's samples at S set to zero (code 0x88)."""
+    T, F, N, k = 50, 1, 6, 3
+    samples, _ = _flag_frame(82, T, F, N, 0.0)
+    inv = np.zeros((T, F, N), bool)
+    S = [0, 7, 8, 9, 31, 49]
+    inv[S, 0, k] = True
+    vis, cnt = oracle.correlate_flagged(samples, pack_flags(inv), lib=lib)
+    for i in range(N):
+        for j in range(i, N):
+            want = T - len(S) if k in (i, j) else T
+            assert cnt[0, oracle.tri_index(i, j, N)] == want, (i, j)
+    z = samples.copy()
+    z[S, 0, k] = 0x88
+    assert np.array_equal(vis, oracle.correlate(z, lib=lib))
+
+
+def pin_flag_numpy(lib):
+    """Counts as the Gram matrix of the validity mask, and V as X X^H of the
+    samples multiplied by the mask, both with numpy on random flags."""
+    T, F, N = 45, 3, 37
+    samples, inv = _flag_frame(83, T, F, N, 0.3)
+    valid = (~inv).astype(np.int64)                                  # [T][F][N]
+    x = _as_complex((samples >> 4).astype(np.int64) - 8, (samples & 15).astype(np.int64) - 8)
+    xm = np.transpose(x * valid, (1, 2, 0))                          # [F][N][T]
+    vm = np.transpose(valid, (1, 2, 0))
+    full_v = xm @ np.conj(np.transpose(xm, (0, 2, 1)))
+    full_c = vm @ np.transpose(vm, (0, 2, 1))
+    vis, cnt = oracle.correlate_flagged(samples, pack_flags(inv), lib=lib)
+    assert np.array_equal(vis, _packed_from_full(np.rint(full_v.real) + 1j * np.rint(full_v.imag)))
+    iu, ju = np.triu_indices(N)
+    assert np.array_equal(cnt, full_c[:, iu, ju])
+
+
+def pin_flag_constant_renormalises(lib):
+    """Every valid sample equals c: V_ij = C_ij |c|^2, so renormalising to the
+    full integration (scale T) gives exactly T |c|^2 wherever a pair is valid."""
+    T, F, N = 64, 2, 9
+    c_re, c_im = 3, -5
+    samples = encode(np.full((T, F, N), c_re), np.full((T, F, N), c_im))
+    _, inv = _flag_frame(84, T, F, N, 0.45)
+    inv[:, 1, 4] = True                                              # no valid pair at all
+    vis, cnt = oracle.correlate_flagged(samples, pack_flags(inv), lib=lib)
+    norm = oracle.normalize(vis, cnt, T)
+    p = c_re * c_re + c_im * c_im
+    want = np.where(cnt[..., None] > 0, np.array([T * p, 0.0]), 0.0).astype(np.float32)
+    assert np.array_equal(norm, want)
+    assert (cnt[1, oracle.tri_index(4, 4, N)] == 0) and (cnt < T).any()
+
+
+FLAG_PINS = (pin_flag_none_and_all, pin_flag_single_input, pin_flag_numpy,
+             pin_flag_constant_renormalises)
 
 FAST_PINS = (pin_counts, pin_worked_example, pin_extremes, pin_constant, pin_single_tone,
              pin_two_tone, pin_gram_invariants, pin_time_additivity, pin_symmetries,

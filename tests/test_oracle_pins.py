@@ -31,6 +31,25 @@ def test_planted_shift_mistake_is_caught(mutant, tmp_path):
     assert failed, f"mutant {mutant} passed every shift pin"
 
 
+@pytest.mark.parametrize("pin", pins.FLAG_PINS, ids=lambda p: p.__name__)
+def test_flag_pin(pin, oracle_lib):
+    pin(oracle_lib)
+
+
+@pytest.mark.parametrize("mutant", obuild.FLAG_MUTANTS + ("CONJ", "INDEX", "NIBBLE"))
+def test_planted_flag_mistake_is_caught(mutant, tmp_path):
+    """A copy of the oracle with a planted mistake fails at least one flag pin."""
+    path = obuild.build(mutant, outdir=str(tmp_path))
+    lib = oracle.load(path=path)
+    failed = []
+    for pin in pins.FLAG_PINS:
+        try:
+            pin(lib)
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, f"mutant {mutant} passed every flag pin"
+
+
 @pytest.mark.parametrize("mutant", obuild.MUTANTS)
 def test_planted_mistake_is_caught(mutant, tmp_path):
     """A copy of the oracle with one planted mistake fails at least one pin."""
