@@ -48,9 +48,9 @@ def parse():
                          "count for scaling the HBM counters of a profiler run)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
-    ap.add_argument("--forms", default="f8,gated,shifted,batched,stream",
+    ap.add_argument("--forms", default="f8,gated,shifted,flagged,batched,stream",
                     help="other forms reported beside the headline line (comma list of f8, "
-                         "gated, shifted, batched, stream; empty for none)")
+                         "gated, shifted, flagged, batched, stream; empty for none)")
     ap.add_argument("--stream-frames", type=int, default=1000)
     return ap.parse_args()
 
@@ -130,6 +130,37 @@ def bench_shifted(d, w, steps, torch, D_max=60000):
             out[name] = {"ms_per_frame": ms, "cmac_per_s": w.cmac / (ms / 1e3),
                          "pct_int8_peak": 100.0 * 8.0 * w.cmac / (ms / 1e3) / 1e12 / PEAK_TOPS["i8"]}
     del ext
+    return out
+
+
+def bench_flagged(d, w, steps, torch):
+    """Flagged data on the same frame, for two seeded flag recipes: pathfinder
+    (rare faults: 0.1% of packets lost, 0.1% of input blocks saturated, 1e-5 of
+    samples overflowed) and heavy (5% of packets lost, 2% of input blocks
+    saturated).  Reports the time of a whole flagged call (scan, correlation,
+    event correlation, counts) and the rows that needed the event path."""
+    import numpy as np
+
+    import synth
+    from paper_1503_06202_amd import Plan
+
+    vis = torch.empty(vis_shape_of(w), dtype=torch.int32, device=d.device)
+    counts = torch.empty((w.F, w.baselines), dtype=torch.int32, device=d.device)
+    frame = d.clone()  # flagged samples are zeroed in place
+    out = {"workload": w.name}
+    with Plan(w.N, w.F, w.T, flagged=True) as p:
+        for k, recipe in enumerate(("pathfinder", "heavy")):
+            fl = synth.gen_flags(w.T, w.F, w.N, 20 + k, recipe)
+            per_row = np.bitwise_count(fl).sum(axis=-1)            # invalid inputs per (t, f)
+            multi = int((per_row >= 2).sum(axis=0).max())
+            flags = torch.from_numpy(fl.view(np.int32)).to(d.device)
+            ms = _time_calls(lambda: p.correlate_flagged(frame, flags, vis, counts),
+                             max(3, steps // 4), torch)
+            out[recipe] = {"ms_per_frame": ms, "invalid_fraction": float(per_row.sum()) / (w.T * w.F * w.N),
+                           "event_rows_max_channel": (multi + 1) // 2,
+                           "pct_int8_peak": 100.0 * 8.0 * w.cmac / (ms / 1e3) / 1e12 / PEAK_TOPS["i8"]}
+            del flags
+    del frame
     return out
 
 
@@ -346,6 +377,9 @@ def main():
     if "shifted" in forms:
         _log("bench: shifted form")
         extra["shifted"] = bench_shifted(d, w, args.steps, torch)
+    if "flagged" in forms:
+        _log("bench: flagged form")
+        extra["flagged"] = bench_flagged(d, w, args.steps, torch)
     if "batched" in forms:
         _log("bench: batched form")
         extra["batched"] = bench_batched(max(3, args.steps // 4), torch)

@@ -172,6 +172,53 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t *samples, int N, int F, in
  */
 int xeng_plan_set_delays(xeng_plan_t p, const int32_t *delays, int D_max);
 
+/*
+ * Flagged data (Sec. IV-A, "Data Flow"): packets lost on the way from the
+ * F-engine, and its flags for ADC saturation or channelizer overflow, mark
+ * samples as invalid; the count of such data renormalises the integrated
+ * matrices.  A flagged sample takes no part in the integration:
+ *   vis[f][b(i,j)]    = sum over t with x[t][f][i] and x[t][f][j] both valid
+ *                       of x_i conj(x_j),
+ *   counts[f][b(i,j)] = the number of such t (int32 [F][N(N+1)/2]).
+ *
+ * xeng_plan_flagged: a plan as xeng_plan (it also serves xeng_correlate) that
+ * owns the count workspace, allocated here: an event frame of T_max x F x N
+ * bytes (as much as a frame), an int32 matrix of vis's size and about 12 F N
+ * bytes of counters.
+ * Errors: as xeng_plan; XENG_ENOMEM / XENG_EHIP when allocation fails.
+ *
+ * xeng_correlate_flagged:
+ *   samples  device uint8 [T][F][N], MODIFIED: every flagged sample is set to
+ *            0x88 (value 0) before the correlation reads the frame.
+ *   flags    device uint32 [T][F][ceil(N / 32)]: bit (i % 32) of word i / 32
+ *            set = sample (t, f, i) invalid; bits of inputs >= N are ignored.
+ *   vis      as xeng_correlate; counts as above (both overwritten, or added to
+ *            with XENG_ACCUMULATE).
+ * Asynchronous on `stream`, with no host synchronisation.  Rows with one
+ * invalid input are counted per input; rows with several become rows of an
+ * event frame, which the int8 MFMA kernel correlates: identical rows within a
+ * block of 64 (a saturated input, a lost packet) take one or two event rows,
+ * distinct ones half a row each.  A frame whose rows all differ and all have
+ * several invalid inputs costs about half a frame more.
+ * Not available while time shifting is set (XENG_EPLAN).
+ * Errors: XENG_EINVAL (NULL pointer, N, F or T < 1), XENG_EPLAN (not a flagged
+ * plan, shifting set, N or F other than planned, T > T_max), XENG_EOVERFLOW,
+ * XENG_EHIP.
+ *
+ * xeng_normalize: renormalised visibilities, float32 [F][N(N+1)/2][2],
+ *   out = vis * scale / counts  (in float64, rounded once to float32),
+ * and 0 where counts is 0.  scale = the number of samples integrated gives
+ * the sums a loss-free integration would have had; scale = 1 the mean product
+ * per valid sample.  N and F are the plan's; any single-instance plan serves.
+ * Errors: XENG_EINVAL (NULL pointer, scale not finite and > 0), XENG_EPLAN
+ * (batch plan), XENG_EHIP.
+ */
+int xeng_plan_flagged(xeng_plan_t *out, int N, int F, int T_max, unsigned flags);
+int xeng_correlate_flagged(xeng_plan_t p, uint8_t *samples, const uint32_t *flags, int N, int F,
+                           int T, int32_t *vis, int32_t *counts, void *stream);
+int xeng_normalize(xeng_plan_t p, const int32_t *vis, const int32_t *counts, double scale,
+                   float *out, void *stream);
+
 /* Free a plan (NULL is accepted).  Waits for nothing: the caller must not
  * destroy a plan with work still in flight on its stream. */
 int xeng_destroy(xeng_plan_t p);

@@ -33,7 +33,7 @@ EXPORTS = (
     "xeng_version", "xeng_strerror", "xeng_plan", "xeng_correlate", "xeng_plan_set_tuning",
     "xeng_destroy", "xeng_plan_error", "xeng_plan_batch", "xeng_correlate_batch",
     "xeng_correlate_batch_graph", "xeng_plan_gated", "xeng_correlate_gated",
-    "xeng_plan_set_delays",
+    "xeng_plan_set_delays", "xeng_plan_flagged", "xeng_correlate_flagged", "xeng_normalize",
 )
 
 
@@ -84,6 +84,12 @@ def lib() -> ctypes.CDLL:
     L.xeng_correlate_gated.restype = ci
     L.xeng_plan_set_delays.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ci]
     L.xeng_plan_set_delays.restype = ci
+    L.xeng_plan_flagged.argtypes = [ctypes.POINTER(vp), ci, ci, ci, ctypes.c_uint]
+    L.xeng_plan_flagged.restype = ci
+    L.xeng_correlate_flagged.argtypes = [vp, vp, vp, ci, ci, ci, vp, vp, vp]
+    L.xeng_correlate_flagged.restype = ci
+    L.xeng_normalize.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
+    L.xeng_normalize.restype = ci
     _lib = L
     return L
 

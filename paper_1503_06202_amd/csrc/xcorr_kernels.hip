@@ -778,6 +778,7 @@ __global__ void __launch_bounds__(NTHREADS, 2) xcorr_gated_kernel(GatedArgs a) {
   tile_of(p, a.nt, I, J);
   const long long NB = (long long)a.N * (a.N + 1) / 2;
   const int r0 = a.gate_off[g], r1 = a.gate_off[g + 1];
+  if (a.skip_empty && r1 == r0) return;  // uniform over the workgroup, before any barrier
   tile_body<FORM, ALIGNED, false, SHIFT>(a.samples, a.vis + (long long)g * a.F * NB * 2, a.N,
                                          a.row_stride, NB, f, I, J,
                                          RunList{a.runs + r0, r1 - r0}, a.write_mode, lds,

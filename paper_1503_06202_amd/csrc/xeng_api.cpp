@@ -66,6 +66,15 @@ struct xeng_plan_s {
   bool shift = false;
   int* d_seg_delay = nullptr;
   int* d_blk_delay = nullptr;
+
+  // flagged data (xeng_plan_flagged): event frame, its correlation and counters
+  bool flagged = false;
+  long long flag_cap = 0;  // event rows per channel
+  int flag_nseg = 0;       // launch segments of the event correlation
+  uint8_t* d_fU = nullptr;
+  int32_t* d_fX = nullptr;
+  int* d_fint = nullptr;   // cnt [F], single [F N], n [F N], R [1], gate_off [2 nseg]
+  int2* d_fruns = nullptr;
 };
 
 namespace {
@@ -428,9 +437,106 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t* samples, int N, int F, in
     a.row_stride = (long long)F * N;
     a.seg_delay = p->shift ? p->d_seg_delay : nullptr;
     a.blk_delay = p->shift ? p->d_blk_delay : nullptr;
+    a.skip_empty = 0;
     e = xeng::launch_gated(a, p->form, aligned, s);
     if (e != hipSuccess) return hip_fail(p, e, "gated correlation kernel launch");
   }
+  return XENG_OK;
+}
+
+// Event rows a frame of T samples can need per channel: a block of rows never
+// takes more event rows than it has rows with several invalid inputs.
+static long long flag_rows(int T) { return T; }
+
+int xeng_plan_flagged(xeng_plan_t* out, int N, int F, int T_max, unsigned flags) {
+  if (!out) return XENG_EINVAL;
+  *out = nullptr;
+  xeng_plan_t p = nullptr;
+  int rc = xeng_plan(&p, N, F, T_max, flags);
+  if (rc != XENG_OK) return rc;
+  p->flagged = true;
+  p->flag_cap = flag_rows(T_max);
+  p->flag_nseg = (int)((p->flag_cap + XENG_I8_SEG_MAX - 1) / XENG_I8_SEG_MAX);
+  const long long NB = (long long)N * (N + 1) / 2;
+  const long long nint = (long long)F + 2LL * F * N + 1 + 2LL * p->flag_nseg;
+  hipError_t e = hipMalloc((void**)&p->d_fU, (size_t)(p->flag_cap * F * N));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_fX, (size_t)(F * NB * 2) * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_fint, (size_t)nint * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_fruns, (size_t)p->flag_nseg * sizeof(int2));
+  if (e != hipSuccess) {
+    rc = e == hipErrorOutOfMemory ? XENG_ENOMEM : XENG_EHIP;
+    (void)hipGetLastError();
+    xeng_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return XENG_OK;
+}
+
+int xeng_correlate_flagged(xeng_plan_t p, uint8_t* samples, const uint32_t* flags, int N, int F,
+                           int T, int32_t* vis, int32_t* counts, void* stream) {
+  if (!p || !samples || !flags || !vis || !counts || N < 1 || F < 1 || T < 1) return XENG_EINVAL;
+  if (p->kind != PLAN_SINGLE || !p->flagged || p->shift) return XENG_EPLAN;
+  if (T > XENG_T_EXACT_MAX) return XENG_EOVERFLOW;
+  if (N != p->N || F != p->F || T > p->T_max) return XENG_EPLAN;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  xeng::FlagArgs a;
+  a.samples = samples;
+  a.flags = flags;
+  a.N = N;
+  a.F = F;
+  a.T = T;
+  a.W = (N + 31) / 32;
+  a.U = p->d_fU;
+  a.cap = flag_rows(T);
+  a.cnt = p->d_fint;
+  a.single = a.cnt + F;
+  a.n = a.single + (long long)F * N;
+  a.R = a.n + (long long)F * N;
+  a.fgate_off = a.R + 1;
+  a.X = p->d_fX;
+  a.fruns = p->d_fruns;
+  a.counts = counts;
+  const int nseg = (int)((a.cap + XENG_I8_SEG_MAX - 1) / XENG_I8_SEG_MAX);
+  hipError_t e = xeng::launch_flag_scan(a, nseg, XENG_I8_SEG_MAX, s);
+  if (e != hipSuccess) return hip_fail(p, e, "flag scan launch");
+  // the frame, now with every flagged sample zero
+  int rc = xeng_correlate(p, samples, N, F, T, vis, stream);
+  if (rc != XENG_OK) return rc;
+  // the event rows: Re X_ij = rows where i and j are both invalid
+  const bool aligned = (N % 16 == 0) && ((long long)F * N <= (1LL << 25));
+  for (int k = 0; k < nseg; ++k) {
+    xeng::GatedArgs g;
+    g.samples = p->d_fU;
+    g.vis = p->d_fX;
+    g.N = N;
+    g.F = F;
+    g.G = 1;
+    g.nt = (N + kTile - 1) / kTile;
+    g.tiles_per_chan = (int)tiles_per_channel(N);
+    g.write_mode = k > 0 ? xeng::WM_ADD : xeng::WM_STORE;
+    g.gate_off = a.fgate_off + 2 * k;
+    g.runs = p->d_fruns;
+    g.row_stride = (long long)F * N;
+    g.seg_delay = nullptr;
+    g.blk_delay = nullptr;
+    g.skip_empty = 1;
+    e = xeng::launch_gated(g, XENG_FORM_I8, aligned, s);
+    if (e != hipSuccess) return hip_fail(p, e, "event correlation kernel launch");
+  }
+  e = xeng::launch_flag_counts(a, p->accumulate ? 1 : 0, s);
+  if (e != hipSuccess) return hip_fail(p, e, "flag count launch");
+  return XENG_OK;
+}
+
+int xeng_normalize(xeng_plan_t p, const int32_t* vis, const int32_t* counts, double scale,
+                   float* out, void* stream) {
+  if (!p || !vis || !counts || !out || !(scale > 0.0) || !(scale < 1e300)) return XENG_EINVAL;
+  if (p->kind != PLAN_SINGLE) return XENG_EPLAN;
+  const long long n = (long long)p->F * p->N * (p->N + 1) / 2;
+  hipError_t e = xeng::launch_normalize(vis, counts, n, scale, out,
+                                        static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(p, e, "normalize launch");
   return XENG_OK;
 }
 
@@ -663,6 +769,10 @@ int xeng_destroy(xeng_plan_t p) {
   if (p->h_runs) (void)hipHostFree(p->h_runs);
   if (p->d_seg_delay) (void)hipFree(p->d_seg_delay);
   if (p->d_blk_delay) (void)hipFree(p->d_blk_delay);
+  if (p->d_fU) (void)hipFree(p->d_fU);
+  if (p->d_fX) (void)hipFree(p->d_fX);
+  if (p->d_fint) (void)hipFree(p->d_fint);
+  if (p->d_fruns) (void)hipFree(p->d_fruns);
   delete p;
   return XENG_OK;
 }

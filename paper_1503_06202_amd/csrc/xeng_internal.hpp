@@ -52,6 +52,7 @@ struct GatedArgs {
   long long row_stride;
   const int* seg_delay;   // time shifting, as in TileArgs
   const int* blk_delay;
+  int skip_empty;         // 1: a gate without runs leaves its output untouched
 };
 
 hipError_t launch_gated(const GatedArgs& a, int form, bool aligned, hipStream_t stream);
@@ -63,6 +64,34 @@ hipError_t launch_zero_tiles(int32_t* vis, int N, int tiles_per_chan, int nt, in
 // a.nt = ceil(N / 128), a.tiles_per_chan = wide tiles per channel.
 hipError_t launch_wide(const TileArgs& a, int form, hipStream_t stream);
 hipError_t launch_zero(int32_t* p, long long n, hipStream_t stream);
+
+// Flagged data: the scan, pad and count kernels around the correlation.
+struct FlagArgs {
+  uint8_t* samples;        // device [T][F][N]; flagged samples are set to 0x88
+  const uint32_t* flags;   // device [T][F][W]; bit i % 32 of word i / 32 = invalid
+  int N, F, T, W;          // W = ceil(N / 32)
+  uint8_t* U;              // device [cap][F][N]: event rows, two flagged rows each
+  long long cap;           // event rows available per channel
+  int* cnt;                // device [F]: event rows used per channel
+  int* single;             // device [F][N]: rows whose only invalid input is i
+  int* n;                  // device [F][N]: invalid samples per input
+  int* R;                  // device [1]: event rows correlated (max of cnt, <= cap)
+  int32_t* X;              // device [F][N(N+1)/2][2]: correlation of U
+  int* fgate_off;          // device [2 nseg]: run table of the event correlation
+  int2* fruns;             // device [nseg]
+  int32_t* counts;         // device [F][N(N+1)/2]: valid pairs per baseline
+};
+
+// Clear the per-call counters, scan the flags (zeroing flagged samples and
+// building U), then pad U and write R and the run table (nseg segments of seg
+// rows).
+hipError_t launch_flag_scan(const FlagArgs& a, int nseg, int seg, hipStream_t stream);
+// After the correlation of U into X: invalid counts per input, then counts.
+hipError_t launch_flag_counts(const FlagArgs& a, int accumulate, hipStream_t stream);
+// out[e] = vis[e] * scale / counts[e] (float64, rounded to float32), 0 where
+// counts[e] == 0; n baselines.
+hipError_t launch_normalize(const int32_t* vis, const int32_t* counts, long long n, double scale,
+                            float* out, hipStream_t stream);
 
 // One work item of the batched persistent kernel.
 struct BatchItem {

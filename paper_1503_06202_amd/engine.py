@@ -62,18 +62,24 @@ class Plan:
     f32 partial sums flushed to int32 every <= 32768 samples).  With
     ``accumulate`` the frame's sums are added to ``vis``.  With ``gates`` > 0
     the plan can also gate the output into up to that many buffers
-    (``correlate_gated``).
+    (``correlate_gated``); with ``flagged`` it can correlate frames with
+    invalid samples and count the valid pairs (``correlate_flagged``).
     """
 
     def __init__(self, N: int, F: int, T_max: int, form: str = "i8", accumulate: bool = False,
-                 split_t: int = 0, kernel: int = 0, gates: int = 0):
+                 split_t: int = 0, kernel: int = 0, gates: int = 0, flagged: bool = False):
         if form not in FORMS:
             raise ValueError(f"form must be one of {sorted(FORMS)}")
+        if gates and flagged:
+            raise ValueError("a plan is either gated or flagged")
         self.N, self.F, self.T_max, self.form, self.accumulate = N, F, T_max, form, accumulate
-        self.gates = gates
+        self.gates, self.flagged = gates, flagged
         flags = FORMS[form] | (_lib.XENG_ACCUMULATE if accumulate else 0)
         h = ctypes.c_void_p()
-        if gates:
+        if flagged:
+            _lib.check(_lib.lib().xeng_plan_flagged(ctypes.byref(h), int(N), int(F), int(T_max),
+                                                    flags), "xeng_plan_flagged")
+        elif gates:
             _lib.check(_lib.lib().xeng_plan_gated(ctypes.byref(h), int(N), int(F), int(T_max),
                                                   int(gates), flags), "xeng_plan_gated")
         else:
@@ -150,6 +156,64 @@ class Plan:
             _stream_handle(stream))
         _lib.check(rc, "xeng_correlate_gated", self._h.value)
         return vis
+
+    def correlate_flagged(self, samples: torch.Tensor, flags: torch.Tensor,
+                          vis: Optional[torch.Tensor] = None, counts: Optional[torch.Tensor] = None,
+                          stream: Optional[torch.cuda.Stream] = None):
+        """Visibilities and valid-pair counts of a frame with invalid samples.
+
+        ``flags`` is a device int32/uint32-sized tensor [T][F][ceil(N/32)] of
+        flag words (bit i % 32 of word i // 32 set = sample invalid).  Flagged
+        samples of ``samples`` are set to 0x88 in place.  Returns ``(vis,
+        counts)``: int32 [F][B][2] and int32 [F][B].
+        """
+        T, F, N = _check_samples(samples)
+        W = (N + 31) // 32
+        if (flags.dtype not in (torch.int32, torch.uint32) or tuple(flags.shape) != (T, F, W)
+                or not flags.is_cuda or not flags.is_contiguous()
+                or flags.device != samples.device):
+            raise ValueError(f"flags must be a contiguous 32-bit tensor {(T, F, W)} on the "
+                             "samples' GPU")
+        if vis is None or counts is None:
+            if self.accumulate:
+                raise ValueError("an accumulating plan needs the vis and counts to add into")
+        if vis is None:
+            vis = torch.empty(vis_shape(N, F), dtype=torch.int32, device=samples.device)
+        else:
+            _check_vis(vis, N, F, samples.device)
+        cshape = (F, num_baselines(N))
+        if counts is None:
+            counts = torch.empty(cshape, dtype=torch.int32, device=samples.device)
+        elif (counts.dtype != torch.int32 or tuple(counts.shape) != cshape or not counts.is_cuda
+              or not counts.is_contiguous() or counts.device != samples.device):
+            raise ValueError(f"counts must be a contiguous int32 {cshape} tensor on the "
+                             "samples' GPU")
+        rc = _lib.lib().xeng_correlate_flagged(self._h, samples.data_ptr(), flags.data_ptr(), N, F,
+                                               T, vis.data_ptr(), counts.data_ptr(),
+                                               _stream_handle(stream))
+        _lib.check(rc, "xeng_correlate_flagged", self._h.value)
+        return vis, counts
+
+    def normalize(self, vis: torch.Tensor, counts: torch.Tensor, scale: float,
+                  out: Optional[torch.Tensor] = None,
+                  stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """Renormalised visibilities float32 [F][B][2]: vis * scale / counts
+        (float64, rounded once), 0 where counts == 0."""
+        N, F = self.N, self.F
+        _check_vis(vis, N, F, vis.device)
+        cshape = (F, num_baselines(N))
+        if (counts.dtype != torch.int32 or tuple(counts.shape) != cshape or not counts.is_cuda
+                or not counts.is_contiguous() or counts.device != vis.device):
+            raise ValueError(f"counts must be a contiguous int32 {cshape} tensor on vis's GPU")
+        if out is None:
+            out = torch.empty(vis_shape(N, F), dtype=torch.float32, device=vis.device)
+        elif (out.dtype != torch.float32 or tuple(out.shape) != vis_shape(N, F)
+              or not out.is_cuda or not out.is_contiguous() or out.device != vis.device):
+            raise ValueError(f"out must be a contiguous float32 {vis_shape(N, F)} tensor")
+        rc = _lib.lib().xeng_normalize(self._h, vis.data_ptr(), counts.data_ptr(), float(scale),
+                                       out.data_ptr(), _stream_handle(stream))
+        _lib.check(rc, "xeng_normalize", self._h.value)
+        return out
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

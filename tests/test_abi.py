@@ -106,6 +106,34 @@ def test_gated_validation_needs_no_gpu(L):
         L.xeng_destroy(hp)
 
 
+def test_flagged_validation_needs_no_gpu(L):
+    h = ctypes.c_void_p()
+    assert L.xeng_plan_flagged(None, 64, 2, 1000, 0) == _lib.XENG_EINVAL
+    assert L.xeng_plan_flagged(ctypes.byref(h), 0, 2, 1000, 0) == _lib.XENG_EINVAL
+    assert L.xeng_plan_flagged(ctypes.byref(h), 64, 2, 1000, 1 << 12) == _lib.XENG_EINVAL
+    assert L.xeng_plan_flagged(ctypes.byref(h), 64, 2, 1 << 24, 0) == _lib.XENG_EOVERFLOW
+    assert not h.value
+    rc, hp = _plan(L, 64, 2, 1000)
+    assert rc == 0
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced
+    try:
+        f = L.xeng_correlate_flagged
+        assert f(None, dummy, dummy, 64, 2, 10, dummy, dummy, None) == _lib.XENG_EINVAL
+        assert f(hp, dummy, None, 64, 2, 10, dummy, dummy, None) == _lib.XENG_EINVAL
+        assert f(hp, dummy, dummy, 64, 2, 10, dummy, None, None) == _lib.XENG_EINVAL
+        assert f(hp, dummy, dummy, 64, 2, 0, dummy, dummy, None) == _lib.XENG_EINVAL
+        # a plan made by xeng_plan has no count workspace
+        assert f(hp, dummy, dummy, 64, 2, 10, dummy, dummy, None) == _lib.XENG_EPLAN
+        n = L.xeng_normalize
+        assert n(None, dummy, dummy, 1.0, dummy, None) == _lib.XENG_EINVAL
+        assert n(hp, dummy, None, 1.0, dummy, None) == _lib.XENG_EINVAL
+        assert n(hp, dummy, dummy, 0.0, dummy, None) == _lib.XENG_EINVAL
+        assert n(hp, dummy, dummy, float("nan"), dummy, None) == _lib.XENG_EINVAL
+        assert n(hp, dummy, dummy, float("inf"), dummy, None) == _lib.XENG_EINVAL
+    finally:
+        L.xeng_destroy(hp)
+
+
 def test_delay_validation_needs_no_gpu(L):
     rc, h = _plan(L, 40, 2, 1000)
     assert rc == 0
