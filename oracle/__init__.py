@@ -14,7 +14,7 @@ forms for constant, single-tone and two-tone inputs, Gram-matrix invariants,
 numpy complex128 ``X @ X^H``, pure-Python brute force, the exhaustive 256 x 256
 code pairs and the int32 boundary.  The gated variant is pinned by summing its
 gates back to the ungated result and by brute force; the shifted and flagged
-variants have pins of their own.
+variants and the beamformer have pins of their own.
 """
 from __future__ import annotations
 
@@ -57,6 +57,9 @@ def load(mutant: Optional[str] = None, path: Optional[str] = None) -> ctypes.CDL
     lib.oracle_correlate_flagged.argtypes = [u8p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_int,
                                              ctypes.c_int, ctypes.c_int, i64p, i64p]
     lib.oracle_correlate_flagged.restype = ctypes.c_int
+    lib.oracle_beamform.argtypes = [u8p, ctypes.POINTER(ctypes.c_int8), ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, ctypes.c_int, i64p]
+    lib.oracle_beamform.restype = ctypes.c_int
     lib.oracle_threads.restype = ctypes.c_int
     _LIBS[key] = lib
     return lib
@@ -178,6 +181,28 @@ def normalize(vis: np.ndarray, counts: np.ndarray, scale: float) -> np.ndarray:
     with np.errstate(divide="ignore", invalid="ignore"):
         out = np.where(c > 0, v * float(scale) / c, 0.0)
     return out.astype(np.float32)
+
+
+def beamform(samples: np.ndarray, weights: np.ndarray,
+             lib: Optional[ctypes.CDLL] = None) -> np.ndarray:
+    """Beams int64 ``[T][F][B][2]``: ``y = sum_n w[f][b][n] x[t][f][n]``.
+
+    ``weights`` is int8 ``[F][B][N][2]`` (re, im), applied without a conjugate.
+    """
+    s = np.ascontiguousarray(samples, dtype=np.uint8)
+    T, F, N = s.shape
+    w = np.ascontiguousarray(weights, dtype=np.int8)
+    if w.ndim != 4 or w.shape[0] != F or w.shape[2] != N or w.shape[3] != 2:
+        raise ValueError("weights must be int8 [F][B][N][2]")
+    B = w.shape[1]
+    out = np.zeros((T, F, B, 2), dtype=np.int64)
+    lib = lib or load()
+    rc = lib.oracle_beamform(s.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                             w.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)), N, F, T, B,
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise ValueError(f"oracle_beamform failed ({rc})")
+    return out
 
 
 def correlate_pairs(samples: np.ndarray, f: np.ndarray, i: np.ndarray, j: np.ndarray,

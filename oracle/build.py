@@ -15,6 +15,7 @@ SRC = os.path.join(HERE, "xeng_oracle.c")
 MUTANTS = ("NIBBLE", "OFFSET", "INDEX", "CONJ", "DROP", "TLAST")
 SHIFT_MUTANTS = ("SHIFT",)  # planted mistakes of the time-shifted mode only
 FLAG_MUTANTS = ("FLAG",)    # planted mistakes of the flagged mode only
+BEAM_MUTANTS = ("BEAMCONJ",)  # planted mistakes of the beamformer only
 
 
 def lib_path(mutant: str | None = None, outdir: str | None = None) -> str:
@@ -28,7 +29,7 @@ def build(mutant: str | None = None, outdir: str | None = None, quiet: bool = Tr
     cmd = [cc, "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11",
            "-Wall", "-Wextra", "-o", out + ".tmp", SRC]
     if mutant:
-        if mutant not in MUTANTS + SHIFT_MUTANTS + FLAG_MUTANTS:
+        if mutant not in MUTANTS + SHIFT_MUTANTS + FLAG_MUTANTS + BEAM_MUTANTS:
             raise ValueError(f"unknown mutant {mutant}")
         cmd.insert(1, f"-DORACLE_MUTANT_{mutant}")
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -281,6 +281,47 @@ int oracle_correlate_flagged(const uint8_t *samples, const uint32_t *flags, int 
 }
 
 /*
+ * Discrete beamforming (Sec. IV-C, "Discrete Beamforming"): the data of all
+ * inputs are phase-shifted and summed, so that signals from one direction add
+ * in phase; the summed signal is written out at the sample cadence.  For every
+ * time t, channel f and beam b,
+ *
+ *     y[t][f][b] = sum over n of w[f][b][n] * x[t][f][n]
+ *
+ * with complex integer weights (the phases, scaled and rounded by the caller)
+ * applied as given, without a conjugate.  weights: int8 [F][B][N][2] (re, im);
+ * out: int64 [T][F][B][2] (re, im).
+ */
+int oracle_beamform(const uint8_t *samples, const int8_t *weights, int N, int F, int T, int B,
+                    int64_t *out) {
+    if (!samples || !weights || !out || N < 1 || F < 1 || T < 0 || B < 1) return -1;
+#pragma omp parallel for schedule(static)
+    for (int t = 0; t < T; ++t) {
+        for (int f = 0; f < F; ++f) {
+            const uint8_t *x = samples + ((int64_t)t * F + f) * N;
+            for (int b = 0; b < B; ++b) {
+                const int8_t *w = weights + (((int64_t)f * B + b) * N) * 2;
+                int64_t re = 0, im = 0;
+                for (int n = 0; n < N; ++n) {
+                    const int64_t xr = nib_real(x[n]), xi = nib_imag(x[n]);
+#ifdef ORACLE_MUTANT_BEAMCONJ
+                    const int64_t wr = w[2 * n], wi = -w[2 * n + 1];   /* planted mistake: conj(w) */
+#else
+                    const int64_t wr = w[2 * n], wi = w[2 * n + 1];
+#endif
+                    re += wr * xr - wi * xi;
+                    im += wr * xi + wi * xr;
+                }
+                int64_t *o = out + (((int64_t)t * F + f) * B + b) * 2;
+                o[0] = re;
+                o[1] = im;
+            }
+        }
+    }
+    return 0;
+}
+
+/*
  * Selected baselines only: out[k] = V_{f[k]}[i[k]][j[k]] as (re, im), summed
  * over t in [0, T) straight from the sample bytes (the same definition as
  * above, one baseline at a time), for checking full-size frames at sampled

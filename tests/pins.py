@@ -351,6 +351,64 @@ def pin_flag_constant_renormalises(lib):
     assert (cnt[1, oracle.tri_index(4, 4, N)] == 0) and (cnt < T).any()
 
 
+# ------------------------------------- discrete beamforming (Sec. IV-C)
+def _beam_case(seed, T, F, N, B):
+    rng = np.random.default_rng(seed)
+    samples = rng.integers(0, 256, (T, F, N), dtype=np.uint8)
+    weights = rng.integers(-127, 128, (F, B, N, 2)).astype(np.int8)
+    return samples, weights
+
+
+def _x(samples):
+    return _as_complex((samples >> 4).astype(np.int64) - 8, (samples & 15).astype(np.int64) - 8)
+
+
+def pin_beam_selects_and_rotates(lib):
+    """A beam whose only weight is 1 at input k is input k's signal; weight i
+    rotates it by 90 degrees (i x = -Im x + i Re x); weight 0 gives 0."""
+    T, F, N, B, k = 20, 2, 9, 3, 4
+    samples, _ = _beam_case(91, T, F, N, B)
+    w = np.zeros((F, B, N, 2), np.int8)
+    w[:, 0, k, 0] = 1          # beam 0: x_k
+    w[:, 1, k, 1] = 1          # beam 1: i x_k
+    y = oracle.beamform(samples, w, lib=lib)
+    re = (samples[:, :, k] >> 4).astype(np.int64) - 8
+    im = (samples[:, :, k] & 15).astype(np.int64) - 8
+    assert np.array_equal(y[:, :, 0, 0], re) and np.array_equal(y[:, :, 0, 1], im)
+    assert np.array_equal(y[:, :, 1, 0], -im) and np.array_equal(y[:, :, 1, 1], re)
+    assert not y[:, :, 2].any()
+
+
+def pin_beam_numpy(lib):
+    """y = W x per channel and time with numpy complex arithmetic (exact)."""
+    T, F, N, B = 17, 3, 21, 5
+    samples, w = _beam_case(92, T, F, N, B)
+    wc = _as_complex(w[..., 0].astype(np.int64), w[..., 1].astype(np.int64))   # [F][B][N]
+    y = np.einsum("fbn,tfn->tfb", wc, _x(samples))
+    got = oracle.beamform(samples, w, lib=lib)
+    assert np.array_equal(got[..., 0], np.rint(y.real).astype(np.int64))
+    assert np.array_equal(got[..., 1], np.rint(y.imag).astype(np.int64))
+
+
+def pin_beam_power_is_visibility_form(lib):
+    """A beam's power summed over time is the quadratic form of the
+    correlator's output: sum_t |y_b|^2 = sum_ij w_i conj(w_j) V_ij, with V from
+    the oracle's correlation (itself pinned above)."""
+    T, F, N, B = 40, 2, 12, 4
+    samples, w = _beam_case(93, T, F, N, B)
+    y = oracle.beamform(samples, w, lib=lib)
+    power = (y[..., 0] ** 2 + y[..., 1] ** 2).sum(axis=0)                         # [F][B]
+    V = oracle.correlate(samples, full=True, lib=lib)                             # [F][N][N][2]
+    Vc = V[..., 0] + 1j * V[..., 1]
+    wc = w[..., 0].astype(np.float64) + 1j * w[..., 1].astype(np.float64)
+    q = np.einsum("fbi,fij,fbj->fb", wc, Vc, np.conj(wc))
+    assert np.array_equal(power, np.rint(q.real).astype(np.int64))
+    assert np.allclose(q.imag, 0)
+
+
+BEAM_PINS = (pin_beam_selects_and_rotates, pin_beam_numpy, pin_beam_power_is_visibility_form)
+
+
 FLAG_PINS = (pin_flag_none_and_all, pin_flag_single_input, pin_flag_numpy,
              pin_flag_constant_renormalises)
 

@@ -50,6 +50,25 @@ def test_planted_flag_mistake_is_caught(mutant, tmp_path):
     assert failed, f"mutant {mutant} passed every flag pin"
 
 
+@pytest.mark.parametrize("pin", pins.BEAM_PINS, ids=lambda p: p.__name__)
+def test_beam_pin(pin, oracle_lib):
+    pin(oracle_lib)
+
+
+@pytest.mark.parametrize("mutant", obuild.BEAM_MUTANTS + ("NIBBLE", "OFFSET"))
+def test_planted_beam_mistake_is_caught(mutant, tmp_path):
+    """A copy of the oracle with a planted mistake fails at least one beam pin."""
+    path = obuild.build(mutant, outdir=str(tmp_path))
+    lib = oracle.load(path=path)
+    failed = []
+    for pin in pins.BEAM_PINS:
+        try:
+            pin(lib)
+        except AssertionError:
+            failed.append(pin.__name__)
+    assert failed, f"mutant {mutant} passed every beam pin"
+
+
 @pytest.mark.parametrize("mutant", obuild.MUTANTS)
 def test_planted_mistake_is_caught(mutant, tmp_path):
     """A copy of the oracle with one planted mistake fails at least one pin."""
