@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 METRIC = ("complex MACs/s and % int8 MFMA peak at N=2048; channels sustained real-time; "
           "p99 frame latency")
 PEAK_TOPS = {"i8": 5000.0, "f8": 5000.0}   # dense MFMA peaks of MI355X (int8 TOP/s, FP8 TFLOP/s)
+HBM_GBPS = 8000.0                           # HBM3E bandwidth of MI355X, GB/s
 SAMPLE_PERIOD_S = 21.47 / 2 ** 23          # one sample per channel every 2.56 us
 CHANNEL_MHZ = 400.0 / 1024                 # 1024 channels over 400 MHz
 
@@ -48,9 +49,9 @@ def parse():
                          "count for scaling the HBM counters of a profiler run)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
-    ap.add_argument("--forms", default="f8,gated,shifted,flagged,batched,stream",
+    ap.add_argument("--forms", default="f8,gated,shifted,flagged,beams,batched,stream",
                     help="other forms reported beside the headline line (comma list of f8, "
-                         "gated, shifted, flagged, batched, stream; empty for none)")
+                         "gated, shifted, flagged, beams, batched, stream; empty for none)")
     ap.add_argument("--stream-frames", type=int, default=1000)
     return ap.parse_args()
 
@@ -161,6 +162,31 @@ def bench_flagged(d, w, steps, torch):
                            "pct_int8_peak": 100.0 * 8.0 * w.cmac / (ms / 1e3) / 1e12 / PEAK_TOPS["i8"]}
             del flags
     del frame
+    return out
+
+
+def bench_beams(d, w, steps, torch, beam_counts=(16, 32, 64)):
+    """Discrete beamforming on the same frame: B phased beams (seeded
+    pointings, 127 e^{-i phi} weights) written at the sample cadence.  The path
+    is bound by HBM: algorithmic bytes are the frame (T F N) plus the beams
+    (8 T F B); every 32 beams read the frame once."""
+    import synth
+    from paper_1503_06202_amd import Plan
+
+    out = {"workload": w.name}
+    for B in beam_counts:
+        y = torch.empty((w.T, w.F, B, 2), dtype=torch.int32, device=d.device)
+        with Plan(w.N, w.F, w.T, beams=B) as p:
+            p.set_weights(synth.gen_beam_weights(w.F, B, w.N, 7))
+            ms = _time_calls(lambda: p.beamform(d, y), max(3, steps // 2), torch)
+        nbytes = w.T * w.F * w.N + 8 * w.T * w.F * B
+        passes = -(-2 * B // 64)
+        out[f"B{B}"] = {"ms_per_frame": ms, "algorithmic_bytes": nbytes,
+                        "hbm_GBps": nbytes / (ms / 1e3) / 1e9,
+                        "hbm_frac": nbytes / (ms / 1e3) / 1e9 / HBM_GBPS,
+                        "frame_reads": passes,
+                        "int8_tops": 8.0 * B * w.N * w.T * w.F / (ms / 1e3) / 1e12}
+        del y
     return out
 
 
@@ -380,6 +406,9 @@ def main():
     if "flagged" in forms:
         _log("bench: flagged form")
         extra["flagged"] = bench_flagged(d, w, args.steps, torch)
+    if "beams" in forms:
+        _log("bench: beamforming form")
+        extra["beams"] = bench_beams(d, w, args.steps, torch)
     if "batched" in forms:
         _log("bench: batched form")
         extra["batched"] = bench_batched(max(3, args.steps // 4), torch)

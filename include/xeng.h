@@ -75,6 +75,7 @@ enum {
 #define XENG_F8_FLUSH_MAX 32768   /* FP8 form: samples per f32 partial sum, at most (sums of
                                      codes 0..15 stay below 2 * 225 * 32768 < 2^24) */
 #define XENG_G_MAX 65536          /* output gating: gate buffers per plan, at most */
+#define XENG_BEAMS_MAX 1024       /* beams per beamforming plan, at most */
 #define XENG_I8_SEG_MAX 524288    /* int8 form, 128 x 128 tiles: samples integrated per launch
                                      (or per batch slice), at most; the int32 sums of codes
                                      then stay below 2^31.  Longer frames are split into
@@ -218,6 +219,39 @@ int xeng_correlate_flagged(xeng_plan_t p, uint8_t *samples, const uint32_t *flag
                            int T, int32_t *vis, int32_t *counts, void *stream);
 int xeng_normalize(xeng_plan_t p, const int32_t *vis, const int32_t *counts, double scale,
                    float *out, void *stream);
+
+/*
+ * Discrete beamforming (Sec. IV-C, "Discrete Beamforming"): the data of all
+ * inputs are phase-shifted and summed so that a signal from one direction adds
+ * in phase, and the sum is written out at the sample cadence:
+ *   beams[t][f][b] = sum over n of w[f][b][n] * x[t][f][n]
+ * (complex; the weights are applied as given, without a conjugate: to point
+ * at a direction, pass w = A e^{-i phi_n} rounded, with phi_n the phase of
+ * that direction's signal at input n and A <= 127).  Exact in int32.
+ *
+ * xeng_plan_beams: a plan for B beams (1..XENG_BEAMS_MAX) over frames of N
+ * inputs, F channels and T <= T_max samples; flags must be 0.  Needs
+ * 515 F N + 256 < 2^31 (longer frames run as several launches).  Allocates the weight operands on the device:
+ * 64 F ceil(N / 64) ceil(2B / 32) KiB.
+ * Errors: XENG_EINVAL (out NULL, sizes out of range, flags), XENG_EOVERFLOW,
+ * XENG_ENOMEM, XENG_EHIP.
+ *
+ * xeng_beam_set_weights: weights, HOST int8 [F][B][N][2] (re, im), each in
+ * -127..127.  They are laid out for the matrix cores on the host and copied
+ * (synchronously) to plan-owned device memory; call again to re-point.
+ * Errors: XENG_EINVAL (NULL, a weight of -128), XENG_EPLAN (not a beam
+ * plan), XENG_EHIP.
+ *
+ * xeng_beamform: beams, device int32 [T][F][B][2] (re, im), from samples
+ * [T][F][N] (device, layout above).  Asynchronous on `stream`.  Every sample
+ * byte is read once per 32 beams (one launch covers up to 32 beams).
+ * Errors: XENG_EINVAL (NULL pointer, sizes < 1), XENG_EPLAN (not a beam plan,
+ * no weights set, N or F other than planned, T > T_max), XENG_EHIP.
+ */
+int xeng_plan_beams(xeng_plan_t *out, int N, int F, int T_max, int B, unsigned flags);
+int xeng_beam_set_weights(xeng_plan_t p, const int8_t *weights);
+int xeng_beamform(xeng_plan_t p, const uint8_t *samples, int N, int F, int T, int32_t *beams,
+                  void *stream);
 
 /* Free a plan (NULL is accepted).  Waits for nothing: the caller must not
  * destroy a plan with work still in flight on its stream. */

@@ -24,6 +24,7 @@ XENG_SHARED_VIS = 1 << 9
 
 XENG_T_EXACT_MAX = (1 << 24) - 1
 XENG_N_MAX = 32768
+XENG_BEAMS_MAX = 1024
 XENG_F8_FLUSH_MAX = 32768
 XENG_I8_SEG_MAX = 524288
 XENG_G_MAX = 65536
@@ -34,6 +35,7 @@ EXPORTS = (
     "xeng_destroy", "xeng_plan_error", "xeng_plan_batch", "xeng_correlate_batch",
     "xeng_correlate_batch_graph", "xeng_plan_gated", "xeng_correlate_gated",
     "xeng_plan_set_delays", "xeng_plan_flagged", "xeng_correlate_flagged", "xeng_normalize",
+    "xeng_plan_beams", "xeng_beam_set_weights", "xeng_beamform",
 )
 
 
@@ -90,6 +92,12 @@ def lib() -> ctypes.CDLL:
     L.xeng_correlate_flagged.restype = ci
     L.xeng_normalize.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp]
     L.xeng_normalize.restype = ci
+    L.xeng_plan_beams.argtypes = [ctypes.POINTER(vp), ci, ci, ci, ci, ctypes.c_uint]
+    L.xeng_plan_beams.restype = ci
+    L.xeng_beam_set_weights.argtypes = [vp, ctypes.POINTER(ctypes.c_int8)]
+    L.xeng_beam_set_weights.restype = ci
+    L.xeng_beamform.argtypes = [vp, vp, ci, ci, ci, vp, vp]
+    L.xeng_beamform.restype = ci
     _lib = L
     return L
 

@@ -386,14 +386,6 @@ __device__ __forceinline__ void write_blocks(int32_t* vis, int N, long long NB, 
   }
 }
 
-// Map a linear workgroup id to (channel, slice, tile) so that consecutive
-// logical ids, which share input rows, run on the same XCD: the dispatcher
-// deals workgroups to the 8 XCDs round robin.
-__device__ __forceinline__ int xcd_logical_id(int b, int G) {
-  const int xcd = b & 7, slot = b >> 3, q = G >> 3, r = G & 7;
-  return xcd * q + (xcd < r ? xcd : r) + slot;
-}
-
 // Row-major upper-triangle tile index p -> (I, J), I <= J < nt.
 __device__ __forceinline__ void tile_of(int p, int nt, int& I, int& J) {
   const float w = 2.0f * nt + 1.0f;

@@ -84,6 +84,14 @@ __device__ __forceinline__ uint32_t neg_i8(uint32_t x) {
   return ((x ^ 0x7F7F7F7Fu) + 0x01010101u) ^ 0x80808080u;
 }
 
+// Map a linear workgroup id b of G to a logical id so that consecutive
+// logical ids, which share input rows, run on the same XCD: the dispatcher
+// deals workgroups to the 8 XCDs round robin.
+__device__ __forceinline__ int xcd_logical_id(int b, int G) {
+  const int xcd = b & 7, slot = b >> 3, q = G >> 3, r = G & 7;
+  return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
 // LDS transpose read of 8 bytes (see above); p must be 8-byte aligned.
 __device__ __forceinline__ v2i lds_tr8(const uint8_t* p) {
   typedef v2i __attribute__((address_space(3))) * lds_v2i;

@@ -75,6 +75,12 @@ struct xeng_plan_s {
   int32_t* d_fX = nullptr;
   int* d_fint = nullptr;   // cnt [F], single [F N], n [F N], R [1], gate_off [2 nseg]
   int2* d_fruns = nullptr;
+
+  // discrete beamforming (xeng_plan_beams): weight operands and offset terms
+  int B = 0, beam_S = 0, beam_nbt = 0;
+  bool beams_ready = false;
+  void* d_wop = nullptr;
+  int* d_bcorr = nullptr;
 };
 
 namespace {
@@ -540,6 +546,108 @@ int xeng_normalize(xeng_plan_t p, const int32_t* vis, const int32_t* counts, dou
   return XENG_OK;
 }
 
+// Beamforming launches: a launch of T rows reads at byte offsets below
+// (T + 512) F N + N + 96 from its first row (512: the most rows of one
+// workgroup), which the segment length keeps below 2^31.
+constexpr long long kBeamRowsMax = 512;
+long long beam_segment(long long row) { return ((1LL << 31) - 1 - 256) / row - kBeamRowsMax - 2; }
+
+int xeng_plan_beams(xeng_plan_t* out, int N, int F, int T_max, int B, unsigned flags) {
+  if (!out) return XENG_EINVAL;
+  *out = nullptr;
+  if (flags != 0 || B < 1 || B > XENG_BEAMS_MAX) return XENG_EINVAL;
+  if (N < 1 || F < 1 || N > XENG_N_MAX || beam_segment((long long)F * N) < 1) return XENG_EINVAL;
+  xeng_plan_t p = nullptr;
+  int rc = xeng_plan(&p, N, F, T_max, 0);
+  if (rc != XENG_OK) return rc;
+  p->B = B;
+  p->beam_S = (N + 63) / 64;
+  p->beam_nbt = (2 * B + 31) / 32;
+  const size_t wop_bytes = (size_t)F * p->beam_S * 4 * p->beam_nbt * 64 * 16;
+  hipError_t e = hipMalloc(&p->d_wop, wop_bytes);
+  if (e == hipSuccess)
+    e = hipMalloc((void**)&p->d_bcorr, (size_t)F * p->beam_nbt * 32 * sizeof(int));
+  if (e != hipSuccess) {
+    rc = e == hipErrorOutOfMemory ? XENG_ENOMEM : XENG_EHIP;
+    (void)hipGetLastError();
+    xeng_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return XENG_OK;
+}
+
+int xeng_beam_set_weights(xeng_plan_t p, const int8_t* weights) {
+  if (!p || !weights) return XENG_EINVAL;
+  if (p->kind != PLAN_SINGLE || p->B < 1) return XENG_EPLAN;
+  const int N = p->N, F = p->F, B = p->B, S = p->beam_S, NBT = p->beam_nbt;
+  const long long nw = (long long)F * B * N * 2;
+  for (long long e = 0; e < nw; ++e)
+    if (weights[e] == -128) return XENG_EINVAL;  // -w must be an int8 as well
+  // Operand of (f, step s, k-step q, tile c, lane l): bytes e = 0..7 weigh the
+  // real code of input 64 s + 32 (l >> 5) + 8 q + e, bytes 8 + e its
+  // imaginary code, for column 32 c + (l & 31) = 2 b + comp of the real
+  // contraction: comp 0 (Re y) takes (w_re, -w_im), comp 1 (Im y) (w_im, w_re).
+  std::vector<int8_t> wop((size_t)F * S * 4 * NBT * 64 * 16, 0);
+  std::vector<int> corr((size_t)F * NBT * 32, 0);
+  for (int f = 0; f < F; ++f)
+    for (int s = 0; s < S; ++s)
+      for (int q = 0; q < 4; ++q)
+        for (int c = 0; c < NBT; ++c)
+          for (int l = 0; l < 64; ++l) {
+            const int col = 32 * c + (l & 31), b = col >> 1, comp = col & 1;
+            if (b >= B) continue;
+            int8_t* o = &wop[(((((size_t)f * S + s) * 4 + q) * NBT + c) * 64 + l) * 16];
+            for (int e = 0; e < 8; ++e) {
+              const int n = 64 * s + 32 * (l >> 5) + 8 * q + e;
+              if (n >= N) continue;
+              const int8_t* w = weights + (((size_t)f * B + b) * N + n) * 2;
+              const int cr = comp == 0 ? w[0] : w[1];
+              const int ci = comp == 0 ? -w[1] : w[0];
+              o[e] = (int8_t)cr;
+              o[8 + e] = (int8_t)ci;
+              corr[(size_t)f * NBT * 32 + col] += 8 * (cr + ci);
+            }
+          }
+  hipError_t e = hipMemcpy(p->d_wop, wop.data(), wop.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_bcorr, corr.data(), corr.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(p, e, "beam weight upload");
+  p->beams_ready = true;
+  return XENG_OK;
+}
+
+int xeng_beamform(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, int32_t* beams,
+                  void* stream) {
+  if (!p || !samples || !beams || N < 1 || F < 1 || T < 1) return XENG_EINVAL;
+  if (p->kind != PLAN_SINGLE || p->B < 1 || !p->beams_ready) return XENG_EPLAN;
+  if (N != p->N || F != p->F || T > p->T_max) return XENG_EPLAN;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long row = (long long)F * N;
+  const long long seg = beam_segment(row);  // >= 1 by the plan's check
+  const bool aligned = (N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples) & 15) == 0);
+  for (long long t0 = 0; t0 < T; t0 += seg) {
+    xeng::BeamArgs a;
+    a.samples = samples + t0 * row;
+    a.beams = beams + t0 * F * 2LL * p->B;
+    a.wop = p->d_wop;
+    a.corr = p->d_bcorr;
+    a.N = N;
+    a.F = F;
+    a.T = (int)std::min<long long>(seg, T - t0);
+    a.B = p->B;
+    a.S = p->beam_S;
+    a.NBT = p->beam_nbt;
+    a.tblocks = 0;
+    for (int c0 = 0; c0 < p->beam_nbt; c0 += 2) {
+      a.c0 = c0;
+      const hipError_t e = xeng::launch_beams(a, std::min(2, p->beam_nbt - c0), aligned, s);
+      if (e != hipSuccess) return hip_fail(p, e, "beamform kernel launch");
+    }
+  }
+  return XENG_OK;
+}
+
 int xeng_plan_batch(xeng_plan_t* out, const xeng_instance* descs, int count, unsigned flags) {
   if (!out) return XENG_EINVAL;
   *out = nullptr;
@@ -773,6 +881,8 @@ int xeng_destroy(xeng_plan_t p) {
   if (p->d_fX) (void)hipFree(p->d_fX);
   if (p->d_fint) (void)hipFree(p->d_fint);
   if (p->d_fruns) (void)hipFree(p->d_fruns);
+  if (p->d_wop) (void)hipFree(p->d_wop);
+  if (p->d_bcorr) (void)hipFree(p->d_bcorr);
   delete p;
   return XENG_OK;
 }

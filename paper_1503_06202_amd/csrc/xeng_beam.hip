@@ -1,0 +1,184 @@
+// Discrete beamforming (Sec. IV-C, "Discrete Beamforming"): the data of all
+// inputs are phase-shifted and summed so that a signal from one direction adds
+// in phase, and the sum is written out at the sample cadence:
+//
+//     y[t][f][b] = sum_n w[f][b][n] x[t][f][n]      (complex, no conjugate)
+//
+// Per channel this is one real int8 contraction on the matrix cores,
+//
+//     Y (T x 2B) = U (T x 2N) . Wop (2N x 2B) - 8 . 1 colsum(Wop),
+//
+// where U holds the offset-binary codes u = v + 8 (0..15) of the real and
+// imaginary parts of every input, column 2b + 0 of Wop holds (w_re, -w_im) and
+// column 2b + 1 holds (w_im, w_re) against (u_re, u_im), and the last term,
+// 8 sum_k Wop[k][c], removes the offsets exactly.
+//
+// The path is bound by HBM: every sample byte is read once (N bytes per time
+// and channel) while the output is 8B bytes.  A workgroup takes one channel
+// and 4 x TT x 32 consecutive times; each wave streams its TT tiles of 32
+// times straight from global memory (buffer loads: out-of-range reads return
+// 0, which the zero weights of absent inputs and the unwritten rows of absent
+// times make harmless), 64 inputs per step with the next step's loads in
+// flight, and takes the weight operands, prepared once per plan in the MFMA
+// lane order, from global memory (they stay in L2).  A lane's A operand for
+// one MFMA is 8 inputs of one time: 8 real codes, then 8 imaginary codes.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xcorr_tile.hpp"
+#include "xeng_internal.hpp"
+
+namespace xeng {
+namespace {
+
+constexpr unsigned kLow4 = 0x0F0F0F0Fu;
+
+// Operand of k-step q (inputs 8q..8q+7 of the lane's 32) from the lane's 32
+// sample bytes.
+__device__ __forceinline__ v4i a_operand(const v4i (&raw)[2], int q) {
+  const uint32_t w0 = (uint32_t)raw[q >> 1][2 * (q & 1)];
+  const uint32_t w1 = (uint32_t)raw[q >> 1][2 * (q & 1) + 1];
+  return v4i{(int)((w0 >> 4) & kLow4), (int)((w1 >> 4) & kLow4), (int)(w0 & kLow4),
+             (int)(w1 & kLow4)};
+}
+
+// The lane's 32 sample bytes of one time: aligned rows take two 16-byte
+// buffer loads, others byte loads.
+template <bool ALIGNED>
+__device__ __forceinline__ void load_row32(v4i (&raw)[2], __amdgpu_buffer_rsrc_t rs, int off) {
+  if (ALIGNED) {
+    raw[0] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    raw[1] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
+  } else {
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        w |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off + 4 * d + e, 0, 0) << (8 * e);
+      raw[d >> 2][d & 3] = (int)w;
+    }
+  }
+}
+
+// NB: beam-component tiles (32 columns of Y each, 1 or 2) of this launch; TT:
+// time tiles of 32 per wave.
+template <int NB, int TT, bool ALIGNED>
+__global__ void __launch_bounds__(256, 2) beam_kernel(BeamArgs a) {
+  const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
+  const int f = logical / a.tblocks;
+  const int tb = logical % a.tblocks;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane >> 5, r = lane & 31;
+  const int tbase = (tb * 4 + wave) * TT * 32;
+  const long long row_stride = (long long)a.F * a.N;
+  // bytes from this channel's first sample to the end of the launch's frame
+  const int nrec = (int)((long long)a.T * row_stride - (long long)f * a.N);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(a.samples + (long long)f * a.N), (short)0, nrec, 0x00020000);
+  const v4i* __restrict__ wop = reinterpret_cast<const v4i*>(a.wop);
+
+  int off[TT];
+#pragma unroll
+  for (int j = 0; j < TT; ++j) off[j] = (int)((long long)(tbase + 32 * j + r) * row_stride) + 32 * h;
+  // weight operand of (step s, k-step q, tile c) for this lane
+  auto wix = [&](int s, int q, int c) {
+    return ((((long long)f * a.S + s) * 4 + q) * a.NBT + a.c0 + c) * 64 + lane;
+  };
+
+  v16i acc[TT][NB];
+#pragma unroll
+  for (int j = 0; j < TT; ++j)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[j][c] = v16i{};
+
+  v4i cur[TT][2], wc[4][NB];
+#pragma unroll
+  for (int j = 0; j < TT; ++j) load_row32<ALIGNED>(cur[j], rs, off[j]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) wc[q][c] = wop[wix(0, q, c)];
+
+  for (int s = 0; s < a.S; ++s) {
+    v4i nxt[TT][2], wn[4][NB];
+    const bool more = s + 1 < a.S;  // uniform
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < TT; ++j) load_row32<ALIGNED>(nxt[j], rs, off[j] + 64 * (s + 1));
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) wn[q][c] = wop[wix(s + 1, q, c)];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < TT; ++j) {
+        const v4i A = a_operand(cur[j], q);
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          acc[j][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, wc[q][c], acc[j][c], 0, 0, 0);
+      }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < TT; ++j) {
+        cur[j][0] = nxt[j][0];
+        cur[j][1] = nxt[j][1];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) wc[q][c] = wn[q][c];
+    }
+  }
+
+  // Y: lane holds column r of each tile and rows 8 (v >> 2) + 4 h + (v & 3)
+  const int ncomp = 2 * a.B;
+  const long long out_row = (long long)a.F * ncomp;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int col = 32 * (a.c0 + c) + r;
+    if (col >= ncomp) continue;
+    const int corr = a.corr[(long long)f * a.NBT * 32 + col];
+    int32_t* out = a.beams + (long long)f * ncomp + col;
+#pragma unroll
+    for (int j = 0; j < TT; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int t = tbase + 32 * j + 8 * (v >> 2) + 4 * h + (v & 3);
+        if (t < a.T) out[(long long)t * out_row] = acc[j][c][v] - corr;
+      }
+  }
+}
+
+template <int NB, int TT, bool ALIGNED>
+hipError_t launch_nb(const BeamArgs& a, hipStream_t stream) {
+  const long long grid = (long long)a.F * a.tblocks;
+  if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((beam_kernel<NB, TT, ALIGNED>), dim3((unsigned)grid), dim3(256), 0, stream,
+                     a);
+  return hipGetLastError();
+}
+
+// Time tiles per wave: registers hold TT x NB accumulators and two steps of
+// operands.
+constexpr int tt_of(int nb, bool aligned) { return !aligned ? 1 : (nb == 1 ? 4 : 2); }
+
+}  // namespace
+
+int beam_rows_per_block(int nb, bool aligned) { return 4 * 32 * tt_of(nb, aligned); }
+
+hipError_t launch_beams(BeamArgs a, int nb, bool aligned, hipStream_t stream) {
+  const int rows = beam_rows_per_block(nb, aligned);
+  a.tblocks = (a.T + rows - 1) / rows;
+  if (nb == 1)
+    return aligned ? launch_nb<1, tt_of(1, true), true>(a, stream)
+                   : launch_nb<1, tt_of(1, false), false>(a, stream);
+  if (nb == 2)
+    return aligned ? launch_nb<2, tt_of(2, true), true>(a, stream)
+                   : launch_nb<2, tt_of(2, false), false>(a, stream);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace xeng

@@ -93,6 +93,27 @@ hipError_t launch_flag_counts(const FlagArgs& a, int accumulate, hipStream_t str
 hipError_t launch_normalize(const int32_t* vis, const int32_t* counts, long long n, double scale,
                             float* out, hipStream_t stream);
 
+// Discrete beamforming: one launch covers the component tiles c0 .. c0 + nb - 1
+// (32 columns of the real contraction each; column 2b + comp is beam b's real
+// (comp 0) or imaginary (comp 1) part) over T rows starting at `samples`.
+struct BeamArgs {
+  const uint8_t* samples;  // device, this launch's first row of [T][F][N]
+  int32_t* beams;          // device, the same row of [T][F][B][2]
+  const void* wop;         // device weight operands [F][S][4][NBT][64 lanes][16 bytes]
+  const int* corr;         // device [F][NBT * 32]: 8 times the column sums of the operands
+  int N, F, T, B;
+  int S;                   // steps of 64 inputs: ceil(N / 64)
+  int NBT;                 // component tiles in all: ceil(2B / 32)
+  int c0;                  // first component tile of this launch
+  int tblocks;             // set by launch_beams
+};
+
+// Rows of one workgroup for nb component tiles per launch.
+int beam_rows_per_block(int nb, bool aligned);
+// nb = 1 or 2 component tiles; aligned: N % 16 == 0 and samples 16-byte
+// aligned.  The host keeps (T + rows per workgroup) F N below 2^31.
+hipError_t launch_beams(BeamArgs a, int nb, bool aligned, hipStream_t stream);
+
 // One work item of the batched persistent kernel.
 struct BatchItem {
   int inst;   // instance index

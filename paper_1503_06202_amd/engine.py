@@ -63,20 +63,28 @@ class Plan:
     ``accumulate`` the frame's sums are added to ``vis``.  With ``gates`` > 0
     the plan can also gate the output into up to that many buffers
     (``correlate_gated``); with ``flagged`` it can correlate frames with
-    invalid samples and count the valid pairs (``correlate_flagged``).
+    invalid samples and count the valid pairs (``correlate_flagged``); with
+    ``beams`` > 0 it is a beamformer for that many beams (``set_weights``,
+    ``beamform``).
     """
 
     def __init__(self, N: int, F: int, T_max: int, form: str = "i8", accumulate: bool = False,
-                 split_t: int = 0, kernel: int = 0, gates: int = 0, flagged: bool = False):
+                 split_t: int = 0, kernel: int = 0, gates: int = 0, flagged: bool = False,
+                 beams: int = 0):
         if form not in FORMS:
             raise ValueError(f"form must be one of {sorted(FORMS)}")
-        if gates and flagged:
-            raise ValueError("a plan is either gated or flagged")
+        if (gates > 0) + bool(flagged) + (beams > 0) > 1:
+            raise ValueError("a plan is gated, flagged or a beamformer, not several")
         self.N, self.F, self.T_max, self.form, self.accumulate = N, F, T_max, form, accumulate
-        self.gates, self.flagged = gates, flagged
+        self.gates, self.flagged, self.beams = gates, flagged, beams
         flags = FORMS[form] | (_lib.XENG_ACCUMULATE if accumulate else 0)
         h = ctypes.c_void_p()
-        if flagged:
+        if beams:
+            if form != "i8" or accumulate:
+                raise ValueError("a beamformer plan takes no form or accumulate option")
+            _lib.check(_lib.lib().xeng_plan_beams(ctypes.byref(h), int(N), int(F), int(T_max),
+                                                  int(beams), 0), "xeng_plan_beams")
+        elif flagged:
             _lib.check(_lib.lib().xeng_plan_flagged(ctypes.byref(h), int(N), int(F), int(T_max),
                                                     flags), "xeng_plan_flagged")
         elif gates:
@@ -215,6 +223,33 @@ class Plan:
         _lib.check(rc, "xeng_normalize", self._h.value)
         return out
 
+    def set_weights(self, weights) -> None:
+        """Beam weights, int8 [F][B][N][2] (re, im) in -127..127, applied
+        without a conjugate (host array; copied to the device)."""
+        import numpy as np
+
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.int8))
+        if w.shape != (self.F, self.beams, self.N, 2):
+            raise ValueError(f"weights must be int8 {(self.F, self.beams, self.N, 2)}")
+        _lib.check(_lib.lib().xeng_beam_set_weights(
+            self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), "xeng_beam_set_weights",
+            self._h.value)
+
+    def beamform(self, samples: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """Beams int32 [T][F][B][2]: y = sum_n w[f][b][n] x[t][f][n]."""
+        T, F, N = _check_samples(samples)
+        shape = (T, F, self.beams, 2)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.int32, device=samples.device)
+        elif (out.dtype != torch.int32 or tuple(out.shape) != shape or not out.is_cuda
+              or not out.is_contiguous() or out.device != samples.device):
+            raise ValueError(f"out must be a contiguous int32 {shape} tensor on the samples' GPU")
+        rc = _lib.lib().xeng_beamform(self._h, samples.data_ptr(), N, F, T, out.data_ptr(),
+                                      _stream_handle(stream))
+        _lib.check(rc, "xeng_beamform", self._h.value)
+        return out
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.lib().xeng_destroy(self._h)
@@ -299,6 +334,33 @@ class BatchPlan:
         fn = _lib.lib().xeng_correlate_batch_graph if graph else _lib.lib().xeng_correlate_batch
         rc = fn(self._h, sp, vp, _stream_handle(stream))
         _lib.check(rc, "xeng_correlate_batch", self._h.value)
+
+    def set_weights(self, weights) -> None:
+        """Beam weights, int8 [F][B][N][2] (re, im) in -127..127, applied
+        without a conjugate (host array; copied to the device)."""
+        import numpy as np
+
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.int8))
+        if w.shape != (self.F, self.beams, self.N, 2):
+            raise ValueError(f"weights must be int8 {(self.F, self.beams, self.N, 2)}")
+        _lib.check(_lib.lib().xeng_beam_set_weights(
+            self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), "xeng_beam_set_weights",
+            self._h.value)
+
+    def beamform(self, samples: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        """Beams int32 [T][F][B][2]: y = sum_n w[f][b][n] x[t][f][n]."""
+        T, F, N = _check_samples(samples)
+        shape = (T, F, self.beams, 2)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.int32, device=samples.device)
+        elif (out.dtype != torch.int32 or tuple(out.shape) != shape or not out.is_cuda
+              or not out.is_contiguous() or out.device != samples.device):
+            raise ValueError(f"out must be a contiguous int32 {shape} tensor on the samples' GPU")
+        rc = _lib.lib().xeng_beamform(self._h, samples.data_ptr(), N, F, T, out.data_ptr(),
+                                      _stream_handle(stream))
+        _lib.check(rc, "xeng_beamform", self._h.value)
+        return out
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

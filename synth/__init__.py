@@ -19,4 +19,5 @@ from .frames import (  # noqa: F401
     stream_frame,
     workload,
 )
+from .beams import gen_beam_weights  # noqa: F401
 from .flags import gen_flags, pack_flags, unpack_flags  # noqa: F401

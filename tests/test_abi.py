@@ -134,6 +134,29 @@ def test_flagged_validation_needs_no_gpu(L):
         L.xeng_destroy(hp)
 
 
+def test_beam_validation_needs_no_gpu(L):
+    h = ctypes.c_void_p()
+    assert L.xeng_plan_beams(None, 64, 2, 1000, 4, 0) == _lib.XENG_EINVAL
+    assert L.xeng_plan_beams(ctypes.byref(h), 64, 2, 1000, 0, 0) == _lib.XENG_EINVAL
+    assert L.xeng_plan_beams(ctypes.byref(h), 64, 2, 1000, _lib.XENG_BEAMS_MAX + 1, 0) == _lib.XENG_EINVAL
+    assert L.xeng_plan_beams(ctypes.byref(h), 64, 2, 1000, 4, 1) == _lib.XENG_EINVAL
+    assert L.xeng_plan_beams(ctypes.byref(h), 32768, 1024, 1000, 4, 0) == _lib.XENG_EINVAL
+    assert not h.value
+    rc, hp = _plan(L, 64, 2, 1000)
+    assert rc == 0
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced
+    try:
+        w = (ctypes.c_int8 * 4)()
+        assert L.xeng_beam_set_weights(None, w) == _lib.XENG_EINVAL
+        assert L.xeng_beam_set_weights(hp, None) == _lib.XENG_EINVAL
+        assert L.xeng_beam_set_weights(hp, w) == _lib.XENG_EPLAN       # not a beam plan
+        assert L.xeng_beamform(None, dummy, 64, 2, 10, dummy, None) == _lib.XENG_EINVAL
+        assert L.xeng_beamform(hp, dummy, 64, 2, 0, dummy, None) == _lib.XENG_EINVAL
+        assert L.xeng_beamform(hp, dummy, 64, 2, 10, dummy, None) == _lib.XENG_EPLAN
+    finally:
+        L.xeng_destroy(hp)
+
+
 def test_delay_validation_needs_no_gpu(L):
     rc, h = _plan(L, 40, 2, 1000)
     assert rc == 0
