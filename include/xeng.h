@@ -232,7 +232,7 @@ int xeng_normalize(xeng_plan_t p, const int32_t *vis, const int32_t *counts, dou
  * xeng_plan_beams: a plan for B beams (1..XENG_BEAMS_MAX) over frames of N
  * inputs, F channels and T <= T_max samples; flags must be 0.  Needs
  * 515 F N + 256 < 2^31 (longer frames run as several launches).  Allocates the weight operands on the device:
- * 64 F ceil(N / 64) ceil(2B / 32) KiB.
+ * 8 F ceil(N / 128) ceil(2B / 32) KiB.
  * Errors: XENG_EINVAL (out NULL, sizes out of range, flags), XENG_EOVERFLOW,
  * XENG_ENOMEM, XENG_EHIP.
  *

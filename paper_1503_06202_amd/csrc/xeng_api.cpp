@@ -547,8 +547,9 @@ int xeng_normalize(xeng_plan_t p, const int32_t* vis, const int32_t* counts, dou
 }
 
 // Beamforming launches: a launch of T rows reads at byte offsets below
-// (T + 512) F N + N + 96 from its first row (512: the most rows of one
-// workgroup), which the segment length keeps below 2^31.
+// (T + 512) F N + N + 160 from its first row (more than the rows of one
+// workgroup past the frame, plus a step past the row), which the segment
+// length keeps below 2^31.
 constexpr long long kBeamRowsMax = 512;
 long long beam_segment(long long row) { return ((1LL << 31) - 1 - 256) / row - kBeamRowsMax - 2; }
 
@@ -561,9 +562,9 @@ int xeng_plan_beams(xeng_plan_t* out, int N, int F, int T_max, int B, unsigned f
   int rc = xeng_plan(&p, N, F, T_max, 0);
   if (rc != XENG_OK) return rc;
   p->B = B;
-  p->beam_S = (N + 63) / 64;
+  p->beam_S = (N + 127) / 128;
   p->beam_nbt = (2 * B + 31) / 32;
-  const size_t wop_bytes = (size_t)F * p->beam_S * 4 * p->beam_nbt * 64 * 16;
+  const size_t wop_bytes = (size_t)F * p->beam_S * 8 * p->beam_nbt * 64 * 16;
   hipError_t e = hipMalloc(&p->d_wop, wop_bytes);
   if (e == hipSuccess)
     e = hipMalloc((void**)&p->d_bcorr, (size_t)F * p->beam_nbt * 32 * sizeof(int));
@@ -585,21 +586,22 @@ int xeng_beam_set_weights(xeng_plan_t p, const int8_t* weights) {
   for (long long e = 0; e < nw; ++e)
     if (weights[e] == -128) return XENG_EINVAL;  // -w must be an int8 as well
   // Operand of (f, step s, k-step q, tile c, lane l): bytes e = 0..7 weigh the
-  // real code of input 64 s + 32 (l >> 5) + 8 q + e, bytes 8 + e its
-  // imaginary code, for column 32 c + (l & 31) = 2 b + comp of the real
-  // contraction: comp 0 (Re y) takes (w_re, -w_im), comp 1 (Im y) (w_im, w_re).
-  std::vector<int8_t> wop((size_t)F * S * 4 * NBT * 64 * 16, 0);
+  // real code of input 128 s + 32 (q >> 1) + 16 (l >> 5) + 8 (q & 1) + e,
+  // bytes 8 + e its imaginary code, for column 32 c + (l & 31) = 2 b + comp of
+  // the real contraction: comp 0 (Re y) takes (w_re, -w_im), comp 1 (Im y)
+  // (w_im, w_re).
+  std::vector<int8_t> wop((size_t)F * S * 8 * NBT * 64 * 16, 0);
   std::vector<int> corr((size_t)F * NBT * 32, 0);
   for (int f = 0; f < F; ++f)
     for (int s = 0; s < S; ++s)
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 8; ++q)
         for (int c = 0; c < NBT; ++c)
           for (int l = 0; l < 64; ++l) {
             const int col = 32 * c + (l & 31), b = col >> 1, comp = col & 1;
             if (b >= B) continue;
-            int8_t* o = &wop[(((((size_t)f * S + s) * 4 + q) * NBT + c) * 64 + l) * 16];
+            int8_t* o = &wop[(((((size_t)f * S + s) * 8 + q) * NBT + c) * 64 + l) * 16];
             for (int e = 0; e < 8; ++e) {
-              const int n = 64 * s + 32 * (l >> 5) + 8 * q + e;
+              const int n = 128 * s + 32 * (q >> 1) + 16 * (l >> 5) + 8 * (q & 1) + e;
               if (n >= N) continue;
               const int8_t* w = weights + (((size_t)f * B + b) * N + n) * 2;
               const int cr = comp == 0 ? w[0] : w[1];

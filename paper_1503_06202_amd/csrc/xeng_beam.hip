@@ -15,13 +15,17 @@
 //
 // The path is bound by HBM: every sample byte is read once (N bytes per time
 // and channel) while the output is 8B bytes.  A workgroup takes one channel
-// and 4 x TT x 32 consecutive times; each wave streams its TT tiles of 32
-// times straight from global memory (buffer loads: out-of-range reads return
-// 0, which the zero weights of absent inputs and the unwritten rows of absent
-// times make harmless), 64 inputs per step with the next step's loads in
-// flight, and takes the weight operands, prepared once per plan in the MFMA
-// lane order, from global memory (they stay in L2).  A lane's A operand for
-// one MFMA is 8 inputs of one time: 8 real codes, then 8 imaginary codes.
+// and 4 x TT x 32 consecutive times; consecutive workgroups take consecutive
+// channels of the same times, so that together they read whole time rows of
+// the frame.  Each wave streams its TT tiles of 32 times straight from global
+// memory, 128 inputs (128 bytes of every row) per step with the next step's
+// loads in flight (buffer loads: out-of-range reads return 0, which the zero
+// weights of absent inputs and the unwritten rows of absent times make
+// harmless), and takes the weight operands, prepared once per plan in the
+// MFMA lane order, from global memory (they stay in L2).  A lane's A operand
+// for one MFMA is 8 inputs of one time: 8 real codes, then 8 imaginary codes;
+// in step s, k-step q (0..7), lane half h holds inputs
+// 128 s + 32 (q >> 1) + 16 h + 8 (q & 1) + 0..7.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -33,30 +37,33 @@ namespace {
 
 constexpr unsigned kLow4 = 0x0F0F0F0Fu;
 
-// Operand of k-step q (inputs 8q..8q+7 of the lane's 32) from the lane's 32
-// sample bytes.
-__device__ __forceinline__ v4i a_operand(const v4i (&raw)[2], int q) {
+// Operand of k-step q (0..7) from the lane's 64 sample bytes of one step.
+__device__ __forceinline__ v4i a_operand(const v4i (&raw)[4], int q) {
   const uint32_t w0 = (uint32_t)raw[q >> 1][2 * (q & 1)];
   const uint32_t w1 = (uint32_t)raw[q >> 1][2 * (q & 1) + 1];
   return v4i{(int)((w0 >> 4) & kLow4), (int)((w1 >> 4) & kLow4), (int)(w0 & kLow4),
              (int)(w1 & kLow4)};
 }
 
-// The lane's 32 sample bytes of one time: aligned rows take two 16-byte
+// The lane's 64 sample bytes of one time and step: bytes 32 i + 16 h .. + 15
+// of the step, i = 0..3 (off includes 16 h).  Aligned rows take four 16-byte
 // buffer loads, others byte loads.
 template <bool ALIGNED>
-__device__ __forceinline__ void load_row32(v4i (&raw)[2], __amdgpu_buffer_rsrc_t rs, int off) {
-  if (ALIGNED) {
-    raw[0] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
-    raw[1] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
-  } else {
+__device__ __forceinline__ void load_step(v4i (&raw)[4], __amdgpu_buffer_rsrc_t rs, int off) {
 #pragma unroll
-    for (int d = 0; d < 8; ++d) {
-      uint32_t w = 0;
+  for (int i = 0; i < 4; ++i) {
+    if (ALIGNED) {
+      raw[i] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 32 * i, 0, 0));
+    } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        w |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off + 4 * d + e, 0, 0) << (8 * e);
-      raw[d >> 2][d & 3] = (int)w;
+      for (int d = 0; d < 4; ++d) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          w |= (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(rs, off + 32 * i + 4 * d + e, 0, 0)
+               << (8 * e);
+        raw[i][d] = (int)w;
+      }
     }
   }
 }
@@ -64,10 +71,10 @@ __device__ __forceinline__ void load_row32(v4i (&raw)[2], __amdgpu_buffer_rsrc_t
 // NB: beam-component tiles (32 columns of Y each, 1 or 2) of this launch; TT:
 // time tiles of 32 per wave.
 template <int NB, int TT, bool ALIGNED>
-__global__ void __launch_bounds__(256, 2) beam_kernel(BeamArgs a) {
+__global__ void __launch_bounds__(256) beam_kernel(BeamArgs a) {
   const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
-  const int f = logical / a.tblocks;
-  const int tb = logical % a.tblocks;
+  const int f = logical % a.F;
+  const int tb = logical / a.F;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int h = lane >> 5, r = lane & 31;
   const int tbase = (tb * 4 + wave) * TT * 32;
@@ -80,10 +87,11 @@ __global__ void __launch_bounds__(256, 2) beam_kernel(BeamArgs a) {
 
   int off[TT];
 #pragma unroll
-  for (int j = 0; j < TT; ++j) off[j] = (int)((long long)(tbase + 32 * j + r) * row_stride) + 32 * h;
+  for (int j = 0; j < TT; ++j)
+    off[j] = (int)((long long)(tbase + 32 * j + r) * row_stride) + 16 * h;
   // weight operand of (step s, k-step q, tile c) for this lane
   auto wix = [&](int s, int q, int c) {
-    return ((((long long)f * a.S + s) * 4 + q) * a.NBT + a.c0 + c) * 64 + lane;
+    return ((((long long)f * a.S + s) * 8 + q) * a.NBT + a.c0 + c) * 64 + lane;
   };
 
   v16i acc[TT][NB];
@@ -92,44 +100,34 @@ __global__ void __launch_bounds__(256, 2) beam_kernel(BeamArgs a) {
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[j][c] = v16i{};
 
-  v4i cur[TT][2], wc[4][NB];
+  v4i cur[TT][4];
 #pragma unroll
-  for (int j = 0; j < TT; ++j) load_row32<ALIGNED>(cur[j], rs, off[j]);
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int c = 0; c < NB; ++c) wc[q][c] = wop[wix(0, q, c)];
-
+  for (int j = 0; j < TT; ++j) load_step<ALIGNED>(cur[j], rs, off[j]);
   for (int s = 0; s < a.S; ++s) {
-    v4i nxt[TT][2], wn[4][NB];
+    v4i nxt[TT][4];
     const bool more = s + 1 < a.S;  // uniform
     if (more) {
 #pragma unroll
-      for (int j = 0; j < TT; ++j) load_row32<ALIGNED>(nxt[j], rs, off[j] + 64 * (s + 1));
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) wn[q][c] = wop[wix(s + 1, q, c)];
+      for (int j = 0; j < TT; ++j) load_step<ALIGNED>(nxt[j], rs, off[j] + 128 * (s + 1));
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 8; ++q) {
+      v4i W[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) W[c] = wop[wix(s, q, c)];
 #pragma unroll
       for (int j = 0; j < TT; ++j) {
         const v4i A = a_operand(cur[j], q);
 #pragma unroll
         for (int c = 0; c < NB; ++c)
-          acc[j][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, wc[q][c], acc[j][c], 0, 0, 0);
+          acc[j][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, W[c], acc[j][c], 0, 0, 0);
       }
+    }
     if (more) {
 #pragma unroll
-      for (int j = 0; j < TT; ++j) {
-        cur[j][0] = nxt[j][0];
-        cur[j][1] = nxt[j][1];
-      }
+      for (int j = 0; j < TT; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) wc[q][c] = wn[q][c];
+        for (int i = 0; i < 4; ++i) cur[j][i] = nxt[j][i];
     }
   }
 
@@ -163,7 +161,7 @@ hipError_t launch_nb(const BeamArgs& a, hipStream_t stream) {
 
 // Time tiles per wave: registers hold TT x NB accumulators and two steps of
 // operands.
-constexpr int tt_of(int nb, bool aligned) { return !aligned ? 1 : (nb == 1 ? 4 : 2); }
+constexpr int tt_of(int nb, bool aligned) { return aligned ? 2 : 1; }
 
 }  // namespace
 

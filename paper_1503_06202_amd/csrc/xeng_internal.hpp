@@ -99,16 +99,16 @@ hipError_t launch_normalize(const int32_t* vis, const int32_t* counts, long long
 struct BeamArgs {
   const uint8_t* samples;  // device, this launch's first row of [T][F][N]
   int32_t* beams;          // device, the same row of [T][F][B][2]
-  const void* wop;         // device weight operands [F][S][4][NBT][64 lanes][16 bytes]
+  const void* wop;         // device weight operands [F][S][8][NBT][64 lanes][16 bytes]
   const int* corr;         // device [F][NBT * 32]: 8 times the column sums of the operands
   int N, F, T, B;
-  int S;                   // steps of 64 inputs: ceil(N / 64)
+  int S;                   // steps of 128 inputs: ceil(N / 128)
   int NBT;                 // component tiles in all: ceil(2B / 32)
   int c0;                  // first component tile of this launch
   int tblocks;             // set by launch_beams
 };
 
-// Rows of one workgroup for nb component tiles per launch.
+// Rows of one workgroup for nb component tiles per launch (at most 256).
 int beam_rows_per_block(int nb, bool aligned);
 // nb = 1 or 2 component tiles; aligned: N % 16 == 0 and samples 16-byte
 // aligned.  The host keeps (T + rows per workgroup) F N below 2^31.
