@@ -166,7 +166,11 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t *samples, int N, int F, in
  *           16 inputs (the unit the kernels load); NULL turns shifting off.
  * Needs (D_max + 64) F N < 2^31.  The delays are copied (synchronously) to
  * plan-owned device memory.  The 128 x 256 tile kernel is not used while
- * shifting.
+ * shifting.  Delays equal within every aligned block of 128 inputs are
+ * applied in the correlation's loads at almost no cost; delays that differ
+ * inside a block make each call first copy the frame, shifted, into a
+ * plan-owned buffer of T_max F N bytes (allocated here, once), which the
+ * correlation then reads unshifted.
  * Errors: XENG_EINVAL (NULL plan, a delay outside 0..D_max, delays that differ
  * within a 16-input group, D_max too large), XENG_EPLAN (batch plan),
  * XENG_ENOMEM, XENG_EHIP.

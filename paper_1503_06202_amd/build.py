@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libxeng.so")
 CEILING = os.path.join(PKG, "mfma_ceiling")
-SOURCES = ("xcorr_kernels.hip", "xeng_flags.hip", "xeng_beam.hip", "xeng_api.cpp")
+SOURCES = ("xcorr_kernels.hip", "xeng_flags.hip", "xeng_beam.hip", "xeng_shift.hip",
+           "xeng_api.cpp")
 ARCH = "gfx950"
 
 

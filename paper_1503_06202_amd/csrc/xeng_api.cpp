@@ -66,6 +66,9 @@ struct xeng_plan_s {
   bool shift = false;
   int* d_seg_delay = nullptr;
   int* d_blk_delay = nullptr;
+  // delays that differ inside a 128-input block: shifted copy of the frame
+  bool shift_copy = false;
+  uint8_t* d_shifted = nullptr;
 
   // flagged data (xeng_plan_flagged): event frame, its correlation and counters
   bool flagged = false;
@@ -255,8 +258,14 @@ int xeng_plan_set_delays(xeng_plan_t p, const int32_t* delays, int D_max) {
     seg[k] = delays[16 * k];
     blk[(16 * k) / kTile] = std::max(blk[(16 * k) / kTile], seg[k]);
   }
+  // Uniform delays within every 128-input block are applied in the kernels'
+  // loads; otherwise the frame is copied, shifted, into plan-owned memory.
+  bool fine = false;
+  for (int k = 0; k < nseg; ++k) fine |= seg[k] != blk[(16 * k) / kTile];
   hipError_t e = hipSuccess;
-  if (!p->d_seg_delay) e = hipMalloc((void**)&p->d_seg_delay, nseg * sizeof(int));
+  if (fine && !p->d_shifted)
+    e = hipMalloc((void**)&p->d_shifted, (size_t)p->T_max * p->F * N);
+  if (e == hipSuccess && !p->d_seg_delay) e = hipMalloc((void**)&p->d_seg_delay, nseg * sizeof(int));
   if (e == hipSuccess && !p->d_blk_delay) e = hipMalloc((void**)&p->d_blk_delay, nt * sizeof(int));
   if (e == hipSuccess)
     e = hipMemcpy(p->d_seg_delay, seg.data(), nseg * sizeof(int), hipMemcpyHostToDevice);
@@ -264,6 +273,7 @@ int xeng_plan_set_delays(xeng_plan_t p, const int32_t* delays, int D_max) {
     e = hipMemcpy(p->d_blk_delay, blk.data(), nt * sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? XENG_ENOMEM : hip_fail(p, e, "delay upload");
   p->shift = true;
+  p->shift_copy = fine;
   return XENG_OK;
 }
 
@@ -285,6 +295,13 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
   int rc = ensure_cu_count(p);
   if (rc != XENG_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // delays: in the loads, or by a shifted copy of the frame
+  const bool kshift = p->shift && !p->shift_copy;
+  if (p->shift && p->shift_copy) {
+    hipError_t e = xeng::launch_shift_copy(samples, p->d_shifted, N, F, T, p->d_seg_delay, s);
+    if (e != hipSuccess) return hip_fail(p, e, "shift copy launch");
+    samples = p->d_shifted;
+  }
 
   const int nt = (N + kTile - 1) / kTile;
   // fast loads: 16-byte row pieces, and per-lane offsets that fit 32 bits
@@ -292,7 +309,7 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
                        ((long long)F * N <= (1LL << 25));
   // wide tiles (128 x 256, one workgroup per CU) only on request and when
   // the rows allow fast loads; 128 x 128 (two workgroups per CU) otherwise
-  const bool wide = aligned && p->kernel == 2 && !p->shift;
+  const bool wide = aligned && p->kernel == 2 && !kshift;
   const long long tpc = wide ? wide_tiles_per_channel(N) : tiles_per_channel(N);
   const int occupancy = wide ? 1 : kOccupancy;
   // The FP8 form integrates at most XENG_F8_FLUSH_MAX samples per launch (f32
@@ -351,8 +368,8 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
     a.tail_slices = tail_slices;
     a.tail_len = tail_len;
     a.tail_mode = xeng::WM_ATOMIC;
-    a.seg_delay = p->shift ? p->d_seg_delay : nullptr;
-    a.blk_delay = p->shift ? p->d_blk_delay : nullptr;
+    a.seg_delay = kshift ? p->d_seg_delay : nullptr;
+    a.blk_delay = kshift ? p->d_blk_delay : nullptr;
     if (nslices > 1) {
       a.write_mode = xeng::WM_ATOMIC;
       if (!add) {
@@ -426,6 +443,12 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t* samples, int N, int F, in
   if (e != hipSuccess) return hip_fail(p, e, "gate table upload");
   p->gate_pending = true;
 
+  const bool kshift = p->shift && !p->shift_copy;
+  if (p->shift && p->shift_copy) {
+    e = xeng::launch_shift_copy(samples, p->d_shifted, N, F, T, p->d_seg_delay, s);
+    if (e != hipSuccess) return hip_fail(p, e, "shift copy launch");
+    samples = p->d_shifted;
+  }
   const bool aligned = (N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples) & 15) == 0) &&
                        ((long long)F * N <= (1LL << 25));
   for (int k = 0; k < nseg; ++k) {
@@ -441,8 +464,8 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t* samples, int N, int F, in
     a.gate_off = p->d_gate_off + (long long)k * (G + 1);
     a.runs = p->d_runs;
     a.row_stride = (long long)F * N;
-    a.seg_delay = p->shift ? p->d_seg_delay : nullptr;
-    a.blk_delay = p->shift ? p->d_blk_delay : nullptr;
+    a.seg_delay = kshift ? p->d_seg_delay : nullptr;
+    a.blk_delay = kshift ? p->d_blk_delay : nullptr;
     a.skip_empty = 0;
     e = xeng::launch_gated(a, p->form, aligned, s);
     if (e != hipSuccess) return hip_fail(p, e, "gated correlation kernel launch");
@@ -879,6 +902,7 @@ int xeng_destroy(xeng_plan_t p) {
   if (p->h_runs) (void)hipHostFree(p->h_runs);
   if (p->d_seg_delay) (void)hipFree(p->d_seg_delay);
   if (p->d_blk_delay) (void)hipFree(p->d_blk_delay);
+  if (p->d_shifted) (void)hipFree(p->d_shifted);
   if (p->d_fU) (void)hipFree(p->d_fU);
   if (p->d_fX) (void)hipFree(p->d_fX);
   if (p->d_fint) (void)hipFree(p->d_fint);

@@ -93,6 +93,11 @@ hipError_t launch_flag_counts(const FlagArgs& a, int accumulate, hipStream_t str
 hipError_t launch_normalize(const int32_t* vis, const int32_t* counts, long long n, double scale,
                             float* out, hipStream_t stream);
 
+// Time shifting by a copy: dst[t][f][16 g + e] = src[t - seg_delay[g]][f][16 g + e]
+// for t < T; rows before src are its history.
+hipError_t launch_shift_copy(const uint8_t* src, uint8_t* dst, int N, int F, int T,
+                             const int* seg_delay, hipStream_t stream);
+
 // Discrete beamforming: one launch covers the component tiles c0 .. c0 + nb - 1
 // (32 columns of the real contraction each; column 2b + comp is beam b's real
 // (comp 0) or imaginary (comp 1) part) over T rows starting at `samples`.

@@ -2,6 +2,10 @@
 IV-C, "Time Shifting"): input n is read D delays[n] samples late; rows
 before the frame come from the history kept in memory right before it.
 
+Two paths: delays equal within every 128-input block are applied in the
+kernels' loads (`block_delays`); delays that differ inside a block go through
+a shifted copy of the frame (`group_delays`).  Both are tested.
+
 A device buffer holds [history; frame]; the plan correlates the view that
 starts D_max rows in.  Expected values come from the oracle only.
 """
@@ -25,6 +29,14 @@ def group_delays(seed, N, D_max, zero_some=True):
     if zero_some:
         g[::3] = 0
     return np.repeat(g, 16)[:N].astype(np.int32)
+
+
+def block_delays(seed, N, D_max):
+    """One delay per aligned block of 128 inputs (the in-load path)."""
+    rng = np.random.default_rng(seed)
+    g = rng.integers(0, D_max + 1, (N + 127) // 128)
+    g[0] = 0
+    return np.repeat(g, 128)[:N].astype(np.int32)
 
 
 def shifted(ext, D, delays, form="i8", vis=None, accumulate=False, gate=None, G=0):
@@ -97,3 +109,37 @@ def test_delays_off_again():
         p.set_delays(None)
         got = p.correlate(dev[D:]).cpu().numpy()
     assert np.array_equal(got, oracle.to_int32(oracle.correlate(ext[D:])))
+
+
+@pytest.mark.parametrize("form", ["i8", "f8"])
+@pytest.mark.parametrize("N", [256, 200])
+def test_block_delays_in_loads(form, N):
+    """Delays constant over each 128-input block: applied in the loads."""
+    D, T, F = 500, 1300, 2
+    ext = rand_ext(69 + N, D + T, F, N)
+    d = block_delays(70, N, D)
+    assert len(set(d.tolist())) > 1
+    assert np.array_equal(shifted(ext, D, d, form), want(ext, D, d))
+
+
+def test_switch_between_paths():
+    """One plan: fine delays (copy), block delays (loads), fine again."""
+    D, T, F, N = 100, 700, 2, 256
+    ext = rand_ext(71, D + T, F, N)
+    dev = torch.from_numpy(ext).to(DEV)
+    with Plan(N, F, T) as p:
+        for d in (group_delays(72, N, D), block_delays(73, N, D), group_delays(74, N, D)):
+            p.set_delays(d, D)
+            got = p.correlate(dev[D:]).cpu().numpy()
+            assert np.array_equal(got, want(ext, D, d))
+
+
+def test_gated_block_delays():
+    D, T, F, N, G = 300, 2000, 1, 256, 2
+    ext = rand_ext(75, D + T, F, N)
+    d = block_delays(76, N, D)
+    gate = (np.arange(T) // 300 % G).astype(np.int32)
+    got = shifted(ext, D, d, gate=gate, G=G)
+    xs = ext[D + np.arange(T)[:, None] - d[None, :], :, np.arange(N)[None, :]]
+    xs = np.ascontiguousarray(np.transpose(xs, (0, 2, 1)))
+    assert np.array_equal(got, oracle.to_int32(oracle.correlate_gated(xs, gate, G)))
