@@ -169,7 +169,7 @@ def bench_beams(d, w, steps, torch, beam_counts=(16, 32, 64)):
     """Discrete beamforming on the same frame: B phased beams (seeded
     pointings, 127 e^{-i phi} weights) written at the sample cadence.  The path
     is bound by HBM: algorithmic bytes are the frame (T F N) plus the beams
-    (8 T F B); every 32 beams read the frame once."""
+    (8 T F B); every 64 beams read the frame once."""
     import synth
     from paper_1503_06202_amd import Plan
 
@@ -180,7 +180,7 @@ def bench_beams(d, w, steps, torch, beam_counts=(16, 32, 64)):
             p.set_weights(synth.gen_beam_weights(w.F, B, w.N, 7))
             ms = _time_calls(lambda: p.beamform(d, y), max(3, steps // 2), torch)
         nbytes = w.T * w.F * w.N + 8 * w.T * w.F * B
-        passes = -(-2 * B // 64)
+        passes = -(-2 * B // 128)   # one launch covers 64 beams
         out[f"B{B}"] = {"ms_per_frame": ms, "algorithmic_bytes": nbytes,
                         "hbm_GBps": nbytes / (ms / 1e3) / 1e9,
                         "hbm_frac": nbytes / (ms / 1e3) / 1e9 / HBM_GBPS,

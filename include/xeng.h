@@ -248,7 +248,7 @@ int xeng_normalize(xeng_plan_t p, const int32_t *vis, const int32_t *counts, dou
  *
  * xeng_beamform: beams, device int32 [T][F][B][2] (re, im), from samples
  * [T][F][N] (device, layout above).  Asynchronous on `stream`.  Every sample
- * byte is read once per 32 beams (one launch covers up to 32 beams).
+ * byte is read once per 64 beams (one launch covers up to 64 beams).
  * Errors: XENG_EINVAL (NULL pointer, sizes < 1), XENG_EPLAN (not a beam plan,
  * no weights set, N or F other than planned, T > T_max), XENG_EHIP.
  */

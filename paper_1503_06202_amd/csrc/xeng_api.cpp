@@ -664,9 +664,9 @@ int xeng_beamform(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, in
     a.S = p->beam_S;
     a.NBT = p->beam_nbt;
     a.tblocks = 0;
-    for (int c0 = 0; c0 < p->beam_nbt; c0 += 2) {
+    for (int c0 = 0; c0 < p->beam_nbt; c0 += 4) {
       a.c0 = c0;
-      const hipError_t e = xeng::launch_beams(a, std::min(2, p->beam_nbt - c0), aligned, s);
+      const hipError_t e = xeng::launch_beams(a, std::min(4, p->beam_nbt - c0), aligned, s);
       if (e != hipSuccess) return hip_fail(p, e, "beamform kernel launch");
     }
   }

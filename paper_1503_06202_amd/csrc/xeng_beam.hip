@@ -21,11 +21,12 @@
 // memory, 128 inputs (128 bytes of every row) per step with the next step's
 // loads in flight (buffer loads: out-of-range reads return 0, which the zero
 // weights of absent inputs and the unwritten rows of absent times make
-// harmless), and takes the weight operands, prepared once per plan in the
-// MFMA lane order, from global memory (they stay in L2).  A lane's A operand
-// for one MFMA is 8 inputs of one time: 8 real codes, then 8 imaginary codes;
-// in step s, k-step q (0..7), lane half h holds inputs
-// 128 s + 32 (q >> 1) + 16 h + 8 (q & 1) + 0..7.
+// harmless).  The weight operands, prepared once per plan in the MFMA lane
+// order, are staged per step into LDS by the whole workgroup (double
+// buffered, one barrier per step), so that the four waves read them once from
+// L2 between them.  A lane's A operand for one MFMA is 8 inputs of one time:
+// 8 real codes, then 8 imaginary codes; in step s, k-step q (0..7), lane half
+// h holds inputs 128 s + 32 (q >> 1) + 16 h + 8 (q & 1) + 0..7.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -68,14 +69,15 @@ __device__ __forceinline__ void load_step(v4i (&raw)[4], __amdgpu_buffer_rsrc_t 
   }
 }
 
-// NB: beam-component tiles (32 columns of Y each, 1 or 2) of this launch; TT:
+// NB: beam-component tiles (32 columns of Y each, 1..4) of this launch; TT:
 // time tiles of 32 per wave.
 template <int NB, int TT, bool ALIGNED>
 __global__ void __launch_bounds__(256) beam_kernel(BeamArgs a) {
+  __shared__ __attribute__((aligned(16))) v4i wl[2][8][NB][64];  // a step's weights, twice
   const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
   const int f = logical % a.F;
   const int tb = logical / a.F;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5, r = lane & 31;
   const int tbase = (tb * 4 + wave) * TT * 32;
   const long long row_stride = (long long)a.F * a.N;
@@ -89,10 +91,14 @@ __global__ void __launch_bounds__(256) beam_kernel(BeamArgs a) {
 #pragma unroll
   for (int j = 0; j < TT; ++j)
     off[j] = (int)((long long)(tbase + 32 * j + r) * row_stride) + 16 * h;
-  // weight operand of (step s, k-step q, tile c) for this lane
-  auto wix = [&](int s, int q, int c) {
-    return ((((long long)f * a.S + s) * 8 + q) * a.NBT + a.c0 + c) * 64 + lane;
+  // A step's weights are 8 x NB x 64 operands; thread tid stages operands
+  // e = tid + 256 k, k < 2 NB, with e = (q NB + c) 64 + lane.
+  auto wsrc = [&](int s, int e) {
+    const int l = e & 63, c = (e >> 6) % NB, q = (e >> 6) / NB;
+    return wop[((((long long)f * a.S + s) * 8 + q) * a.NBT + a.c0 + c) * 64 + l];
   };
+  v4i* const wflat0 = &wl[0][0][0][0];
+  v4i* const wflat1 = &wl[1][0][0][0];
 
   v16i acc[TT][NB];
 #pragma unroll
@@ -100,21 +106,27 @@ __global__ void __launch_bounds__(256) beam_kernel(BeamArgs a) {
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[j][c] = v16i{};
 
-  v4i cur[TT][4];
+  v4i cur[TT][4], wst[2 * NB];
 #pragma unroll
   for (int j = 0; j < TT; ++j) load_step<ALIGNED>(cur[j], rs, off[j]);
+#pragma unroll
+  for (int k = 0; k < 2 * NB; ++k) wflat0[tid + 256 * k] = wsrc(0, tid + 256 * k);
+  __syncthreads();
   for (int s = 0; s < a.S; ++s) {
     v4i nxt[TT][4];
     const bool more = s + 1 < a.S;  // uniform
+    const int b = s & 1;
     if (more) {
 #pragma unroll
       for (int j = 0; j < TT; ++j) load_step<ALIGNED>(nxt[j], rs, off[j] + 128 * (s + 1));
+#pragma unroll
+      for (int k = 0; k < 2 * NB; ++k) wst[k] = wsrc(s + 1, tid + 256 * k);
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       v4i W[NB];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) W[c] = wop[wix(s, q, c)];
+      for (int c = 0; c < NB; ++c) W[c] = wl[b][q][c][lane];
 #pragma unroll
       for (int j = 0; j < TT; ++j) {
         const v4i A = a_operand(cur[j], q);
@@ -124,11 +136,16 @@ __global__ void __launch_bounds__(256) beam_kernel(BeamArgs a) {
       }
     }
     if (more) {
+      // the other buffer was last read in step s - 1, before the last barrier
+      v4i* const wnext = b ? wflat0 : wflat1;
+#pragma unroll
+      for (int k = 0; k < 2 * NB; ++k) wnext[tid + 256 * k] = wst[k];
 #pragma unroll
       for (int j = 0; j < TT; ++j)
 #pragma unroll
         for (int i = 0; i < 4; ++i) cur[j][i] = nxt[j][i];
     }
+    __syncthreads();
   }
 
   // Y: lane holds column r of each tile and rows 8 (v >> 2) + 4 h + (v & 3)
@@ -160,8 +177,14 @@ hipError_t launch_nb(const BeamArgs& a, hipStream_t stream) {
 }
 
 // Time tiles per wave: registers hold TT x NB accumulators and two steps of
-// operands.
-constexpr int tt_of(int nb, bool aligned) { return aligned ? 2 : 1; }
+// sample operands.
+constexpr int tt_of(int nb, bool aligned) { return aligned && nb <= 2 ? 2 : 1; }
+
+template <int NB>
+hipError_t launch_aligned_or_not(const BeamArgs& a, bool aligned, hipStream_t stream) {
+  return aligned ? launch_nb<NB, tt_of(NB, true), true>(a, stream)
+                 : launch_nb<NB, tt_of(NB, false), false>(a, stream);
+}
 
 }  // namespace
 
@@ -170,13 +193,13 @@ int beam_rows_per_block(int nb, bool aligned) { return 4 * 32 * tt_of(nb, aligne
 hipError_t launch_beams(BeamArgs a, int nb, bool aligned, hipStream_t stream) {
   const int rows = beam_rows_per_block(nb, aligned);
   a.tblocks = (a.T + rows - 1) / rows;
-  if (nb == 1)
-    return aligned ? launch_nb<1, tt_of(1, true), true>(a, stream)
-                   : launch_nb<1, tt_of(1, false), false>(a, stream);
-  if (nb == 2)
-    return aligned ? launch_nb<2, tt_of(2, true), true>(a, stream)
-                   : launch_nb<2, tt_of(2, false), false>(a, stream);
-  return hipErrorInvalidValue;
+  switch (nb) {
+    case 1: return launch_aligned_or_not<1>(a, aligned, stream);
+    case 2: return launch_aligned_or_not<2>(a, aligned, stream);
+    case 3: return launch_aligned_or_not<3>(a, aligned, stream);
+    case 4: return launch_aligned_or_not<4>(a, aligned, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace xeng

@@ -115,7 +115,7 @@ struct BeamArgs {
 
 // Rows of one workgroup for nb component tiles per launch (at most 256).
 int beam_rows_per_block(int nb, bool aligned);
-// nb = 1 or 2 component tiles; aligned: N % 16 == 0 and samples 16-byte
+// nb = 1..4 component tiles; aligned: N % 16 == 0 and samples 16-byte
 // aligned.  The host keeps (T + rows per workgroup) F N below 2^31.
 hipError_t launch_beams(BeamArgs a, int nb, bool aligned, hipStream_t stream);
 
