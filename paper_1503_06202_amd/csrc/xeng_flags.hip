@@ -37,7 +37,7 @@ namespace {
 
 constexpr int kRows = 64;                 // time rows per workgroup of the scan
 constexpr int kRowsPerWave = kRows / 4;   // its four waves take 16 rows each,
-constexpr int kBatch = 8;                 // with the loads of 8 rows in flight
+constexpr int kBatch = 4;                 // with the loads of 4 rows in flight
 constexpr unsigned kZero4 = 0x88888888u;  // four samples of value 0 + 0i
 
 // Bits 0..3 of x to bit 0 of bytes 0..3.
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(256) flag_scan_kernel(FlagArgs a) {
   // A. per row: invalid inputs, the first of them and the hash; flagged
   //    samples become zero (code 0x88) so that the correlation skips them.
   //    Wave q takes rows 16 q .. 16 q + 15, lanes the words of a row; the
-  //    loads of 8 rows are issued together.
+  //    loads of kBatch rows are issued together.
 #pragma unroll 1
   for (int h = 0; h < kRowsPerWave; h += kBatch) {
     const int rbase = wave * kRowsPerWave + h;
@@ -234,7 +234,7 @@ __global__ void __launch_bounds__(256) flag_scan_kernel(FlagArgs a) {
   __syncthreads();
 
   // C. exact check: a row whose words differ from its leader's leaves the
-  //    group (loads of 8 rows in flight)
+  //    group (loads of kBatch rows in flight)
 #pragma unroll 1
   for (int h = 0; h < kRowsPerWave; h += kBatch) {
     const int rbase = wave * kRowsPerWave + h;
