@@ -89,10 +89,11 @@ __device__ __forceinline__ void load_pieces_edge(v4i (&raw)[4], const uint8_t* _
   raw[3] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ + 16, t_end, dJ);
 }
 
-// Split the nibbles of a piece and store them, unchanged, into the real and
-// imaginary planes of an LDS operand block (rows = times, as loaded).
+// Store a piece, unchanged, into the LDS plane of its block (rows = times, as
+// loaded).  The nibbles are split after the transpose read (see
+// compute_chunk).
 //
-// The planes hold the offset-binary codes u = v + 8 in 0..15, which both
+// The operands are the offset-binary codes u = v + 8 in 0..15, which both
 // matrix-core forms take as they are: as int8 they are the integers 0..15, and
 // as FP8 e4m3 bytes they are u * 2^-9 (the subnormals 0..7 and the first
 // binade 8..15 lie on one grid), which the MFMA's operand scale of 2^9 turns
@@ -101,18 +102,8 @@ __device__ __forceinline__ void load_pieces_edge(v4i (&raw)[4], const uint8_t* _
 // TileSums): with S_n = sum_t u_n,
 //
 //   sum (u_i - 8)(u_j - 8) = sum u_i u_j - 8 S_i - 8 S_j + 64 T.
-//
-// Staging costs three operations per word for both planes.
 __device__ __forceinline__ void stage_piece(const v4i& raw, uint8_t* __restrict__ dst) {
-  v4i re, im;
-#pragma unroll
-  for (int d = 0; d < 4; ++d) {
-    const uint32_t w = (uint32_t)raw[d];
-    re[d] = (int)((w >> 4) & 0x0F0F0F0Fu);
-    im[d] = (int)(w & 0x0F0F0F0Fu);
-  }
-  *reinterpret_cast<v4i*>(dst) = re;
-  *reinterpret_cast<v4i*>(dst + PLANE) = im;
+  *reinterpret_cast<v4i*>(dst) = raw;
 }
 
 // Piece k of a thread into the stage at `stage` (I block at 0, J block at
@@ -227,15 +218,17 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         if (!COMPUTE && !RT && a != SA) continue;
-        ar[a] = lds_tr8(pa + 16 * s * PROW + 32 * a);
-        am[a] = lds_tr8(pa + PLANE + 16 * s * PROW + 32 * a);
+        const v2i w = lds_tr8(pa + 16 * s * PROW + 32 * a);
+        ar[a] = hi_codes(w);
+        am[a] = lo_codes(w);
         A[a] = v4i{am[a].x, am[a].y, ar[a].x, ar[a].y};
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         if (!COMPUTE && !RT && b != SB) continue;
-        br[b] = lds_tr8(pb + 16 * s * PROW + 32 * b);
-        bm[b] = lds_tr8(pb + PLANE + 16 * s * PROW + 32 * b);
+        const v2i wb = lds_tr8(pb + 16 * s * PROW + 32 * b);
+        br[b] = hi_codes(wb);
+        bm[b] = lo_codes(wb);
         const int c15 = 0x0F0F0F0F;
         const v8i w = v8i{bm[b].x, bm[b].y, br[b].x, br[b].y, bm[b].x ^ c15, bm[b].y ^ c15, 0, 0};
         B[b] = __builtin_shufflevector(w, w, 0, 1, 2, 3);
@@ -269,16 +262,16 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
       for (int a = 0; a < 2; ++a) {
         if (!COMPUTE && !RT && a != SA) continue;
         const uint8_t* q = pa + 32 * s * PROW + 32 * a;
-        const v2i r0 = lds_tr8(q), m0 = lds_tr8(q + PLANE);
-        const v2i r1 = lds_tr8(q + 8 * PROW), m1 = lds_tr8(q + PLANE + 8 * PROW);
+        const v2i w0 = lds_tr8(q), w1 = lds_tr8(q + 8 * PROW);
+        const v2i r0 = hi_codes(w0), m0 = lo_codes(w0), r1 = hi_codes(w1), m1 = lo_codes(w1);
         A[a] = v8i{r0.x, r0.y, m0.x, m0.y, r1.x, r1.y, m1.x, m1.y};
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         if (!COMPUTE && !RT && b != SB) continue;
         const uint8_t* q = pb + 32 * s * PROW + 32 * b;
-        const v2i r0 = lds_tr8(q), m0 = lds_tr8(q + PLANE);
-        const v2i r1 = lds_tr8(q + 8 * PROW), m1 = lds_tr8(q + PLANE + 8 * PROW);
+        const v2i w0 = lds_tr8(q), w1 = lds_tr8(q + 8 * PROW);
+        const v2i r0 = hi_codes(w0), m0 = lo_codes(w0), r1 = hi_codes(w1), m1 = lo_codes(w1);
         B[b] = v8i{r0.x, r0.y, m0.x, m0.y, r1.x, r1.y, m1.x, m1.y};
       }
       if (COMPUTE && (!RT || mfma)) {

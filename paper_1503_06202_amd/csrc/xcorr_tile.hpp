@@ -24,17 +24,19 @@
 // workgroup stages a chunk of KC = 64 samples of two blocks of 128 inputs:
 // every thread loads 16-byte row pieces (sixteen inputs at one time; eight
 // lanes cover a 128-byte row, so every load instruction reads whole cache
-// lines), splits the nibbles and stores the real and imaginary parts into two
-// LDS planes laid out [t][n] as loaded, with no transposition.  An MFMA lane
-// needs eight consecutive samples of one input; the LDS transpose read
+// lines) and stores them unchanged into an LDS plane laid out [t][n] as
+// loaded, one byte per sample, with no transposition.  An MFMA lane needs
+// eight consecutive samples of one input; the LDS transpose read
 // (ds_read_b64_tr_b8) delivers exactly that: within a group of 16 lanes, lane
 // i receives byte i & 7 of the 8 bytes addressed by lanes 2k + (i >> 3),
 // k = 0..7, so lanes addressing rows t0..t0+7 at inputs n0..n0+15 receive,
-// lane by lane, inputs n0+i at times t0..t0+7.  Plane rows are 160 bytes (40
-// banks of 4 bytes): the 32 lanes of a transpose read pass (two 16-lane
-// groups, 8 rows x 16 bytes each, 16 bytes apart) then cover all 64 banks
-// once, and so do the 16 lanes of a staging write pass (two 128-byte rows 4
-// apart).
+// lane by lane, inputs n0+i at times t0..t0+7.  The lane then splits the
+// nibbles of its 8 bytes into 8 real and 8 imaginary codes in registers, so
+// that staging writes and transpose reads move one byte per sample, not two.
+// Plane rows are 160 bytes (40 banks of 4 bytes): the 32 lanes of a transpose
+// read pass (two 16-lane groups, 8 rows x 16 bytes each, 16 bytes apart) then
+// cover all 64 banks once, and so do the 16 lanes of a staging write pass
+// (two 128-byte rows 4 apart).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -51,9 +53,9 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int BT = 128;                   // tile edge (inputs)
 constexpr int KC = 64;                    // samples per staged chunk
 constexpr int PROW = BT + 32;             // bytes per plane row (one time, 128 inputs, padded)
-constexpr int PLANE = KC * PROW;          // one plane (real or imaginary parts of a block)
+constexpr int PLANE = KC * PROW;          // one plane: the sample bytes of a block
 constexpr int NTHREADS = 256;             // 4 waves: 2 x 2 wave tiles of 64 x 64
-constexpr int BLOCK_LDS = 2 * PLANE;      // one operand block: real plane, imaginary plane
+constexpr int BLOCK_LDS = PLANE;          // one operand block
 constexpr int STAGE_LDS = 2 * BLOCK_LDS;  // I block + J block
 constexpr int LDS_BYTES = 2 * STAGE_LDS;  // double buffered
 
@@ -90,6 +92,15 @@ __device__ __forceinline__ uint32_t neg_i8(uint32_t x) {
 __device__ __forceinline__ int xcd_logical_id(int b, int G) {
   const int xcd = b & 7, slot = b >> 3, q = G >> 3, r = G & 7;
   return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
+// The real (high nibble) and imaginary (low nibble) codes of eight sample
+// bytes, one code per byte.
+__device__ __forceinline__ v2i hi_codes(v2i w) {
+  return v2i{(int)(((uint32_t)w.x >> 4) & 0x0F0F0F0Fu), (int)(((uint32_t)w.y >> 4) & 0x0F0F0F0Fu)};
+}
+__device__ __forceinline__ v2i lo_codes(v2i w) {
+  return v2i{(int)((uint32_t)w.x & 0x0F0F0F0Fu), (int)((uint32_t)w.y & 0x0F0F0F0Fu)};
 }
 
 // LDS transpose read of 8 bytes (see above); p must be 8-byte aligned.
