@@ -164,6 +164,7 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t *samples, int N, int F, in
  * frames); they must be readable, and they are read only for d > t.
  *   delays  HOST array of N ints in 0..D_max, one value per aligned group of
  *           16 inputs (the unit the kernels load); NULL turns shifting off.
+ * Replacing delays waits for the device to finish the work in flight.
  * Needs (D_max + 64) F N < 2^31.  The delays are copied (synchronously) to
  * plan-owned device memory.  The 128 x 256 tile kernel is not used while
  * shifting.  Delays equal within every aligned block of 128 inputs are
@@ -242,7 +243,8 @@ int xeng_normalize(xeng_plan_t p, const int32_t *vis, const int32_t *counts, dou
  *
  * xeng_beam_set_weights: weights, HOST int8 [F][B][N][2] (re, im), each in
  * -127..127.  They are laid out for the matrix cores on the host and copied
- * (synchronously) to plan-owned device memory; call again to re-point.
+ * (synchronously, after the device has finished the work in flight) to
+ * plan-owned device memory; call again to re-point.
  * Errors: XENG_EINVAL (NULL, a weight of -128), XENG_EPLAN (not a beam
  * plan), XENG_EHIP.
  *

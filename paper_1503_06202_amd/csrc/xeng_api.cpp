@@ -262,8 +262,9 @@ int xeng_plan_set_delays(xeng_plan_t p, const int32_t* delays, int D_max) {
   // loads; otherwise the frame is copied, shifted, into plan-owned memory.
   bool fine = false;
   for (int k = 0; k < nseg; ++k) fine |= seg[k] != blk[(16 * k) / kTile];
-  hipError_t e = hipSuccess;
-  if (fine && !p->d_shifted)
+  // calls of this plan still in flight on any stream read the old delays
+  hipError_t e = p->shift ? hipDeviceSynchronize() : hipSuccess;
+  if (e == hipSuccess && fine && !p->d_shifted)
     e = hipMalloc((void**)&p->d_shifted, (size_t)p->T_max * p->F * N);
   if (e == hipSuccess && !p->d_seg_delay) e = hipMalloc((void**)&p->d_seg_delay, nseg * sizeof(int));
   if (e == hipSuccess && !p->d_blk_delay) e = hipMalloc((void**)&p->d_blk_delay, nt * sizeof(int));
@@ -634,7 +635,9 @@ int xeng_beam_set_weights(xeng_plan_t p, const int8_t* weights) {
               corr[(size_t)f * NBT * 32 + col] += 8 * (cr + ci);
             }
           }
-  hipError_t e = hipMemcpy(p->d_wop, wop.data(), wop.size(), hipMemcpyHostToDevice);
+  // calls of this plan still in flight on any stream read the old operands
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(p->d_wop, wop.data(), wop.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(p->d_bcorr, corr.data(), corr.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(p, e, "beam weight upload");
