@@ -49,9 +49,10 @@ def parse():
                          "count for scaling the HBM counters of a profiler run)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
-    ap.add_argument("--forms", default="f8,gated,shifted,flagged,beams,batched,stream",
+    ap.add_argument("--forms", default="f8,pathfinder,gated,shifted,flagged,beams,batched,stream",
                     help="other forms reported beside the headline line (comma list of f8, "
-                         "gated, shifted, flagged, beams, batched, stream; empty for none)")
+                         "pathfinder, gated, shifted, flagged, beams, batched, stream; empty for "
+                         "none)")
     ap.add_argument("--stream-frames", type=int, default=1000)
     return ap.parse_args()
 
@@ -187,6 +188,31 @@ def bench_beams(d, w, steps, torch, beam_counts=(16, 32, 64)):
                         "frame_reads": passes,
                         "int8_tops": 8.0 * B * w.N * w.T * w.F / (ms / 1e3) / 1e12}
         del y
+    return out
+
+
+def bench_pathfinder(steps, torch):
+    """The Pathfinder shape (N = 256, F = 64, T = 32768; 512 MiB per frame):
+    only about 1.6x above the int8 ridge, so both the MFMA fraction and the
+    algorithmic HBM rate are reported."""
+    import synth
+    from paper_1503_06202_amd import Plan
+
+    w = synth.workload("pathfinder")
+    frame = synth.gen_frame(w.N, w.F, w.T, w.seed, w.kind)
+    d = torch.from_numpy(frame).to("cuda:0")
+    vis = torch.empty(vis_shape_of(w), dtype=torch.int32, device=d.device)
+    with Plan(w.N, w.F, w.T) as p:
+        ms = _time_calls(lambda: p.correlate(d, vis), steps, torch)
+    nbytes = w.T * w.F * w.N + 8 * w.F * w.baselines
+    ops = 8.0 * w.cmac / (ms / 1e3) / 1e12
+    out = {"workload": w.name, "N": w.N, "F": w.F, "T": w.T, "ms_per_frame": ms,
+           "cmac_per_s": w.cmac / (ms / 1e3), "pct_int8_peak": 100.0 * ops / PEAK_TOPS["i8"],
+           "algorithmic_GBps": nbytes / (ms / 1e3) / 1e9,
+           "hbm_frac": nbytes / (ms / 1e3) / 1e9 / HBM_GBPS,
+           "realtime_channels": w.F * w.T * SAMPLE_PERIOD_S / (ms / 1e3),
+           "sha256": synth.frame_sha256(frame)}
+    del d, vis
     return out
 
 
@@ -385,6 +411,23 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic},
     }
+    out["config"]["sha256"] = synth.frame_sha256(frame)
+    # Host-fed rate, beside (never instead of) the device-resident value: one
+    # copy of the frame from pinned host memory, then the correlation.
+    pinned = torch.from_numpy(frame).pin_memory()
+    h2d = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        d.copy_(pinned, non_blocking=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        h2d.append(e0.elapsed_time(e1))
+    h2d_ms = min(h2d)
+    out["h2d"] = {"frame_bytes": int(d.numel()), "ms": h2d_ms,
+                  "GBps": d.numel() / (h2d_ms / 1e3) / 1e9,
+                  "realtime_channels_with_h2d": w.F * frame_s / ((h2d_ms + ms_step) / 1e3)}
+    del pinned
     if args.calibrate_copy:
         dst = torch.empty_like(d)
         dst.copy_(d)
@@ -397,6 +440,9 @@ def main():
     if "f8" in forms:
         _log("bench: fp8 form")
         extra["fp8"] = bench_fp8(d, w, args.steps, torch)
+    if "pathfinder" in forms:
+        _log("bench: pathfinder shape")
+        extra["pathfinder"] = bench_pathfinder(args.steps, torch)
     if "gated" in forms:
         _log("bench: gated form")
         extra["gated"] = bench_gated(d, w, args.steps, torch)
