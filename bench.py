@@ -311,6 +311,8 @@ def mfma_ceiling():
     reach on this chip at its power limit."""
     import subprocess
 
+    import numpy as np
+
     exe = os.path.join(ROOT, "paper_1503_06202_amd", "mfma_ceiling")
     if not os.path.exists(exe):
         return None
@@ -320,8 +322,54 @@ def mfma_ceiling():
     return json.loads(res.stdout.strip().splitlines()[-1])
 
 
+_ONE_CORE = """
+import sys, time
+import numpy as np
+import oracle
+T, N = int(sys.argv[1]), int(sys.argv[2])
+s = np.frombuffer(sys.stdin.buffer.read(), np.uint8).reshape(T, 1, N)
+lib = oracle.load()
+t0 = time.perf_counter()
+oracle.correlate(s, lib=lib)
+print(time.perf_counter() - t0, oracle.threads(lib))
+"""
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def one_core(frame, w, T1):
+    """The oracle on one thread (OMP_NUM_THREADS=1, a child process) over the
+    first T1 samples of channel 0."""
+    import subprocess
+
+    import numpy as np
+
+    sub = np.ascontiguousarray(frame[:T1, 0, :])
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-c", _ONE_CORE, str(T1), str(w.N)], input=sub.tobytes(),
+                         capture_output=True, env=env, cwd=os.path.dirname(os.path.abspath(__file__)),
+                         timeout=300)
+    if res.returncode != 0:
+        return {"error": res.stderr.decode(errors="replace")[-300:]}
+    dt, nthr = res.stdout.decode().split()[-2:]
+    cmac = T1 * w.baselines
+    return {"value": cmac / float(dt), "unit": "cMAC/s", "cores": int(nthr),
+            "sample": f"channel 0, first {T1} samples ({cmac:.3e} complex MACs, {float(dt):.1f} s)"}
+
+
 def cpu_baseline(frame, w):
-    """The oracle on channel 0 of the same frame, all T samples (1/F of the work)."""
+    """The oracle on channel 0 of the same frame, all T samples (1/F of the
+    work), on every thread OpenMP takes; then on one thread over a shorter
+    stretch of the same channel."""
     import oracle
 
     lib = oracle.load()
@@ -329,10 +377,15 @@ def cpu_baseline(frame, w):
     oracle.correlate(frame, channels=[0], lib=lib)
     dt = time.perf_counter() - t0
     cmac = w.T * w.baselines
-    return {"value": cmac / dt, "unit": "cMAC/s", "cores": oracle.threads(lib), "kind": "oracle",
-            "sample": f"channel 0 of the {w.name} frame, all {w.T} samples "
-                      f"({cmac:.3e} complex MACs, {dt:.1f} s)",
-            "cpu": platform.processor() or platform.machine()}
+    out = {"value": cmac / dt, "unit": "cMAC/s", "cores": oracle.threads(lib), "kind": "oracle",
+           "sample": f"channel 0 of the {w.name} frame, all {w.T} samples "
+                     f"({cmac:.3e} complex MACs, {dt:.1f} s)",
+           "cpu": cpu_model(), "host_cpus": os.cpu_count()}
+    # about 5 s on one thread at the rate just measured, in whole 256-sample steps
+    per_thread = cmac / dt / max(1, out["cores"])
+    T1 = int(min(w.T, max(256, 5.0 * per_thread / w.baselines // 256 * 256)))
+    out["one_core"] = one_core(frame, w, T1)
+    return out
 
 
 def main():
