@@ -49,10 +49,11 @@ def parse():
                          "count for scaling the HBM counters of a profiler run)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
-    ap.add_argument("--forms", default="f8,pathfinder,gated,shifted,flagged,beams,batched,stream",
+    ap.add_argument("--forms",
+                    default="f8,precision,pathfinder,gated,shifted,flagged,beams,batched,stream",
                     help="other forms reported beside the headline line (comma list of f8, "
-                         "pathfinder, gated, shifted, flagged, beams, batched, stream; empty for "
-                         "none)")
+                         "precision, pathfinder, gated, shifted, flagged, beams, batched, stream; "
+                         "empty for none)")
     ap.add_argument("--stream-frames", type=int, default=1000)
     return ap.parse_args()
 
@@ -89,6 +90,32 @@ def bench_fp8(d, w, steps, torch):
     ops = 8.0 * w.cmac / (ms / 1e3) / 1e12
     return {"workload": w.name, "ms_per_frame": ms, "cmac_per_s": w.cmac / (ms / 1e3),
             "tflops": ops, "pct_fp8_peak": 100.0 * ops / PEAK_TOPS["f8"]}
+
+
+def bench_precision(steps, torch):
+    """FP8 beside int8 on the precision workload (N = 2048, F = 16,
+    T = 131072; 4 GiB per frame).  The FP8 form flushes its f32 sums to int32
+    every 32768 samples, i.e. four launches per frame; int8 takes the frame in
+    one launch."""
+    import synth
+    from paper_1503_06202_amd import Plan
+
+    w = synth.workload("precision")
+    t0 = time.perf_counter()
+    frame = synth.gen_frame(w.N, w.F, w.T, w.seed, w.kind)
+    _log(f"bench: precision frame generated in {time.perf_counter() - t0:.1f} s")
+    out = {"workload": w.name, "N": w.N, "F": w.F, "T": w.T, "sha256": synth.frame_sha256(frame)}
+    d = torch.from_numpy(frame).to("cuda:0")
+    del frame
+    vis = torch.empty(vis_shape_of(w), dtype=torch.int32, device=d.device)
+    for form in ("f8", "i8"):
+        with Plan(w.N, w.F, w.T, form=form) as p:
+            ms = _time_calls(lambda: p.correlate(d, vis), max(4, steps // 2), torch)
+        ops = 8.0 * w.cmac / (ms / 1e3) / 1e12
+        out[form] = {"ms_per_frame": ms, "cmac_per_s": w.cmac / (ms / 1e3), "tflops": ops,
+                     "pct_peak": 100.0 * ops / PEAK_TOPS[form]}
+    del d, vis
+    return out
 
 
 def bench_gated(d, w, steps, torch, G=16, period=8192):
@@ -505,6 +532,9 @@ def main():
     if "f8" in forms:
         _log("bench: fp8 form")
         extra["fp8"] = bench_fp8(d, w, args.steps, torch)
+    if "precision" in forms:
+        _log("bench: precision workload, fp8 and int8")
+        extra["precision"] = bench_precision(args.steps, torch)
     if "pathfinder" in forms:
         _log("bench: pathfinder shape")
         extra["pathfinder"] = bench_pathfinder(args.steps, torch)
