@@ -46,7 +46,9 @@ def want(s, w):
 
 
 @pytest.mark.parametrize("N,T,B", [(96, 300, 5), (40, 129, 3), (64, 512, 16), (128, 77, 17),
-                                   (256, 1000, 40), (2048, 200, 64), (17, 33, 1)])
+                                   (256, 1000, 40), (2048, 200, 64), (17, 33, 1),
+                                   (128, 301, 64), (512, 259, 50), (256, 300, 100),
+                                   (48, 200, 57)])
 def test_beams_match_oracle(N, T, B):
     F = 3
     s = rand_frame(200 + N + B, T, F, N)
