@@ -393,20 +393,24 @@ def one_core(frame, w, T1):
             "sample": f"channel 0, first {T1} samples ({cmac:.3e} complex MACs, {float(dt):.1f} s)"}
 
 
-def cpu_baseline(frame, w):
-    """The oracle on channel 0 of the same frame, all T samples (1/F of the
-    work), on every thread OpenMP takes; then on one thread over a shorter
-    stretch of the same channel."""
+def cpu_baseline(frame, w, budget_s=10.0):
+    """The oracle on whole channels of the same frame (all T samples each),
+    channel after channel until about budget_s seconds have run, on every
+    thread OpenMP takes; then on one thread over a shorter stretch of
+    channel 0."""
     import oracle
 
     lib = oracle.load()
-    t0 = time.perf_counter()
-    oracle.correlate(frame, channels=[0], lib=lib)
-    dt = time.perf_counter() - t0
-    cmac = w.T * w.baselines
+    dt, nch = 0.0, 0
+    while nch < w.F and dt < budget_s:
+        t0 = time.perf_counter()
+        oracle.correlate(frame, channels=[nch], lib=lib)
+        dt += time.perf_counter() - t0
+        nch += 1
+    cmac = nch * w.T * w.baselines
     out = {"value": cmac / dt, "unit": "cMAC/s", "cores": oracle.threads(lib), "kind": "oracle",
-           "sample": f"channel 0 of the {w.name} frame, all {w.T} samples "
-                     f"({cmac:.3e} complex MACs, {dt:.1f} s)",
+           "sample": f"channels 0..{nch - 1} of the {w.name} frame ({nch} of {w.F}), all {w.T} "
+                     f"samples each ({cmac:.3e} complex MACs, {dt:.1f} s)",
            "cpu": cpu_model(), "host_cpus": os.cpu_count()}
     # about 5 s on one thread at the rate just measured, in whole 256-sample steps
     per_thread = cmac / dt / max(1, out["cores"])
