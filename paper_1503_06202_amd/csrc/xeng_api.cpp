@@ -132,13 +132,25 @@ long long wide_tiles_per_channel(int N) {
 }
 
 // Time slices per tile.  With W tiles and `slots` resident workgroups, S
-// slices take ceil(W S / slots) rounds of 1/S of the work each; every extra
+// slices take round_cost(W S) rounds of 1/S of the work each; every extra
 // slice costs about 4% more (exact int32 atomic adds into vis, which must be
-// cleared first).  Pick the S that minimises ceil(W S / slots) / S * (1 +
-// 0.04 (S - 1)), keeping slices of at least 1024 samples.
-double slice_cost(long long tiles, int S, long long slots) {
-  const long long rounds = (tiles * S + slots - 1) / slots;
-  return (double)rounds / S * (1.0 + 0.04 * (S - 1));
+// cleared first).  auto_slices picks the S that minimises round_cost(W S) /
+// S * (1 + 0.04 (S - 1)), keeping slices of at least 1024 samples.
+//
+// round_cost: rounds of resident workgroups that `items` work items take on
+// `slots` slots (`occupancy` per CU).  A last round that leaves each CU at
+// most one workgroup costs less than a full one, since that workgroup has the
+// CU to itself: on 192 tiles at N = 256 (512 slots) the timings of 1 to 8
+// slices fit a cost of about 0.6 round for it.
+constexpr double kLoneRound = 0.6;
+double round_cost(long long items, long long slots, int occupancy) {
+  const long long full = items / slots, rem = items % slots;
+  if (rem == 0) return (double)full;
+  return (double)full + (occupancy > 1 && rem * occupancy <= slots ? kLoneRound : 1.0);
+}
+
+double slice_cost(long long tiles, int S, long long slots, int occupancy) {
+  return round_cost(tiles * S, slots, occupancy) / S * (1.0 + 0.04 * (S - 1));
 }
 
 int auto_slices(long long tiles, int T, int cu_count, int occupancy = kOccupancy) {
@@ -147,8 +159,7 @@ int auto_slices(long long tiles, int T, int cu_count, int occupancy = kOccupancy
   int best = 1;
   double best_cost = 1e300;
   for (int S = 1; S <= smax; ++S) {
-    const long long rounds = (tiles * S + slots - 1) / slots;
-    const double cost = (double)rounds / S * (1.0 + 0.04 * (S - 1));
+    const double cost = slice_cost(tiles, S, slots, occupancy);
     if (cost < best_cost - 1e-12) {
       best_cost = cost;
       best = S;
@@ -343,8 +354,8 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
       int tl = (len + St - 1) / St;
       tl = (tl + kChunk - 1) / kChunk * kChunk;
       St = (len + tl - 1) / tl;
-      const double cost_tail = (double)R + slice_cost(rem, St, slots);
-      if (St > 1 && cost_tail < slice_cost(W, nslices, slots) - 1e-9) {
+      const double cost_tail = (double)R + slice_cost(rem, St, slots, occupancy);
+      if (St > 1 && cost_tail < slice_cost(W, nslices, slots, occupancy) - 1e-9) {
         head = R * slots;
         tail_slices = St;
         tail_len = tl;
