@@ -402,7 +402,7 @@ def cpu_baseline(frame, w, budget_s=10.0):
 
     lib = oracle.load()
     dt, nch = 0.0, 0
-    while nch < w.F and dt < budget_s:
+    while nch < w.F and (nch == 0 or dt < budget_s):  # at least one whole channel
         t0 = time.perf_counter()
         oracle.correlate(frame, channels=[nch], lib=lib)
         dt += time.perf_counter() - t0
