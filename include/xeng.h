@@ -143,8 +143,13 @@ int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel);
  * of equal gate, uploaded from the plan's staging; a call first waits for the
  * previous call's upload to finish reading that staging.  Every (channel,
  * tile, gate) is one work item that integrates all runs of its gate: cost
- * grows with the number of runs only through their ragged edges (runs
- * shorter than 64 samples are costly), and the output is written once.
+ * grows with the number of runs only through their ragged edges (a run is
+ * integrated in whole chunks of 64 samples, so runs shorter than 64 samples
+ * are costly), and the output is written once.  A gate whose runs, rounded
+ * up to whole chunks, hold more samples in one launch than one exact
+ * integration may (XENG_F8_FLUSH_MAX in FP8, XENG_I8_SEG_MAX in int8) is
+ * split into work items that add into its buffer with int32 atomics, so that
+ * every sum stays exact however short the runs are.
  * Errors: XENG_EINVAL (NULL pointers, N, F, T or G < 1), XENG_EPLAN (not a
  * gated plan, G > G_max, N or F other than planned, T > T_max),
  * XENG_EOVERFLOW (T > XENG_T_EXACT_MAX), XENG_EHIP.
@@ -164,7 +169,8 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t *samples, int N, int F, in
  * frames); they must be readable, and they are read only for d > t.
  *   delays  HOST array of N ints in 0..D_max, one value per aligned group of
  *           16 inputs (the unit the kernels load); NULL turns shifting off.
- * Replacing delays waits for the device to finish the work in flight.
+ * Replacing delays first waits (on the host) for the plan's last call that
+ * read them: an event recorded on that call's stream, not a device-wide sync.
  * Needs (D_max + 64) F N < 2^31.  The delays are copied (synchronously) to
  * plan-owned device memory.  The 128 x 256 tile kernel is not used while
  * shifting.  Delays equal within every aligned block of 128 inputs are
@@ -243,8 +249,8 @@ int xeng_normalize(xeng_plan_t p, const int32_t *vis, const int32_t *counts, dou
  *
  * xeng_beam_set_weights: weights, HOST int8 [F][B][N][2] (re, im), each in
  * -127..127.  They are laid out for the matrix cores on the host and copied
- * (synchronously, after the device has finished the work in flight) to
- * plan-owned device memory; call again to re-point.
+ * (synchronously, after the plan's last xeng_beamform has finished reading the
+ * previous weights) to plan-owned device memory; call again to re-point.
  * Errors: XENG_EINVAL (NULL, a weight of -128), XENG_EPLAN (not a beam
  * plan), XENG_EHIP.
  *

@@ -17,8 +17,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libxeng.so")
 CEILING = os.path.join(PKG, "mfma_ceiling")
-SOURCES = ("xcorr_kernels.hip", "xeng_flags.hip", "xeng_beam.hip", "xeng_shift.hip",
-           "xeng_api.cpp")
+SOURCES = ("xcorr_plain.hip", "xcorr_gated.hip", "xcorr_batch.hip", "xcorr_wide.hip",
+           "xeng_flags.hip", "xeng_beam.hip", "xeng_shift.hip", "xeng_api.cpp")
+OBJDIR = os.path.join(PKG, "_build")
 ARCH = "gfx950"
 
 
@@ -28,13 +29,24 @@ def hipcc() -> str:
     return p if os.path.exists(p) else "hipcc"
 
 
-def command(out: str = LIB) -> list:
-    return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-fPIC", "-shared", "-std=c++17",
-            "-Wall", "-Wno-unused-result",
-            # keep the compiler from emitting packed FP32 instructions
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", os.path.join(ROOT, "include"),
-            "-o", out] + [os.path.join(CSRC, s) for s in SOURCES]
+FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
+         # keep the compiler from emitting packed FP32 instructions
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-I", os.path.join(ROOT, "include")]
+
+
+def object_path(src: str) -> str:
+    return os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+
+
+def compile_command(src: str) -> list:
+    """One translation unit to an object (the units build in parallel)."""
+    return [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", object_path(src)]
+
+
+def link_command(out: str = LIB) -> list:
+    return [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out] + \
+        [object_path(s) for s in SOURCES]
 
 
 def ceiling_command(out: str = CEILING) -> list:
@@ -54,9 +66,16 @@ def _run(cmd: list, what: str, quiet: bool) -> None:
         print(msg)
 
 
-def build(quiet: bool = True) -> str:
+def build(quiet: bool = True, jobs: int = 0) -> str:
+    from concurrent.futures import ThreadPoolExecutor
+
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), max(1, min(16, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, compile_command(s), s, quiet) for s in SOURCES]:
+            f.result()
     tmp = LIB + ".tmp"
-    _run(command(tmp), "libxeng", quiet)
+    _run(link_command(tmp), "libxeng", quiet)
     os.replace(tmp, LIB)
     tmp = CEILING + ".tmp"
     _run(ceiling_command(tmp), "mfma_ceiling", quiet)

@@ -21,6 +21,9 @@ namespace {
 constexpr int kTile = 128;   // tile edge of the kernels
 constexpr int kChunk = 64;   // samples per staged chunk
 constexpr int kOccupancy = 2;  // workgroups per CU (LDS: 64 KiB each)
+// Output gating: extra work gates one launch segment can need when gates are
+// split (fewer than 2 x 64 = 128; see xeng_correlate_gated).
+constexpr int kSplitMax = 128;
 
 enum PlanKind { PLAN_SINGLE = 1, PLAN_BATCH = 2 };
 
@@ -54,13 +57,18 @@ struct xeng_plan_s {
 
   // output gating (xeng_plan_gated): run tables, pinned staging and device
   int G_max = 0;
-  long long gate_off_cap = 0, runs_cap = 0;  // entries
+  long long gate_off_cap = 0, runs_cap = 0, vgate_cap = 0;  // entries
   int* h_gate_off = nullptr;
   int2* h_runs = nullptr;
+  int2* h_vgate = nullptr;
   int* d_gate_off = nullptr;
   int2* d_runs = nullptr;
+  int2* d_vgate = nullptr;
   hipEvent_t gate_done = nullptr;
   bool gate_pending = false;
+  std::vector<int> gate_count, gate_fill;  // host work space of the run tables, G_max each
+  std::vector<int> gate_zero;              // gates to clear before a split gate adds into them
+  std::vector<int> seg_goff, seg_nvg;      // per launch segment: first table entry, work gates
 
   // time shifting (xeng_plan_set_delays): per-segment delays and block maxima
   bool shift = false;
@@ -79,6 +87,12 @@ struct xeng_plan_s {
   int* d_fint = nullptr;   // cnt [F], single [F N], n [F N], R [1], gate_off [2 nseg]
   int2* d_fruns = nullptr;
 
+  // The delay tables and the beam weight operands are replaced only after the
+  // plan's last call that reads them has finished (a plan has at most one
+  // call in flight): that call records tables_used on its stream.
+  hipEvent_t tables_used = nullptr;
+  bool tables_pending = false;
+
   // discrete beamforming (xeng_plan_beams): weight operands and offset terms
   int B = 0, beam_S = 0, beam_nbt = 0;
   bool beams_ready = false;
@@ -93,6 +107,24 @@ int hip_fail(xeng_plan_t p, hipError_t e, const char* what) {
     p->err = std::string(what) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
   }
   return XENG_EHIP;
+}
+
+// Create the plan's tables_used event if needed, and wait until the plan's
+// last call that read its delay or weight tables has finished.
+hipError_t wait_tables(xeng_plan_t p) {
+  if (!p->tables_used) return hipEventCreateWithFlags(&p->tables_used, hipEventDisableTiming);
+  if (!p->tables_pending) return hipSuccess;
+  const hipError_t e = hipEventSynchronize(p->tables_used);
+  if (e == hipSuccess) p->tables_pending = false;
+  return e;
+}
+
+// After a call that read the tables: mark them in use until `s` gets here.
+int mark_tables(xeng_plan_t p, hipStream_t s) {
+  const hipError_t e = hipEventRecord(p->tables_used, s);
+  if (e != hipSuccess) return hip_fail(p, e, "hipEventRecord");
+  p->tables_pending = true;
+  return XENG_OK;
 }
 
 bool flags_ok(unsigned flags, bool batch = false) {
@@ -172,6 +204,19 @@ int auto_slices(long long tiles, int T, int cu_count, int occupancy = kOccupancy
 // stay exact: f32 below 2^24, int32 below 2^31).
 int segment_max(int form) { return form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : XENG_I8_SEG_MAX; }
 
+// Time slices of a batch instance: S slices of `len` samples (a multiple of
+// kChunk), from its split_t or else the batch's automatic count s_auto; no
+// slice integrates more than segment_max(form) samples.
+void batch_slices(const xeng_instance& d, int s_auto, int form, int& S, int& len) {
+  S = d.split_t > 0 ? d.split_t : std::max(1, std::min(s_auto, d.T / 1024));
+  const int seg_max = segment_max(form);
+  S = std::max(S, (d.T + seg_max - 1) / seg_max);
+  S = std::min(S, (d.T + kChunk - 1) / kChunk);
+  len = (d.T + S - 1) / S;
+  len = (len + kChunk - 1) / kChunk * kChunk;
+  S = (d.T + len - 1) / len;
+}
+
 // Compute units of the current device for a plan being built; without a
 // device (plans can be built and validated on a host with no GPU) the count
 // of an MI355X.  Only the automatic slice count depends on it.
@@ -232,14 +277,29 @@ int xeng_plan_gated(xeng_plan_t* out, int N, int F, int T_max, int G_max, unsign
   const int seg = segment_max(p->form);
   const long long nseg = (T_max + seg - 1) / seg;
   p->G_max = G_max;
-  p->gate_off_cap = nseg * (G_max + 1);
+  try {
+    p->gate_count.assign(G_max, 0);
+    p->gate_fill.assign(G_max, 0);
+    p->gate_zero.assign(G_max, 0);
+    p->seg_goff.assign(nseg, 0);
+    p->seg_nvg.assign(nseg, 0);
+  } catch (const std::bad_alloc&) {
+    xeng_destroy(p);
+    return XENG_ENOMEM;
+  }
+  // A segment has at most G_max + kSplitMax work gates (see xeng_correlate_gated).
+  p->vgate_cap = nseg * ((long long)G_max + kSplitMax);
+  p->gate_off_cap = p->vgate_cap + nseg;
   p->runs_cap = (long long)T_max + nseg;  // at most one run per sample, plus a cut per segment
   hipError_t e = hipHostMalloc((void**)&p->h_gate_off, p->gate_off_cap * sizeof(int),
                                hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&p->h_runs, p->runs_cap * sizeof(int2), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&p->h_vgate, p->vgate_cap * sizeof(int2), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void**)&p->d_gate_off, p->gate_off_cap * sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void**)&p->d_runs, p->runs_cap * sizeof(int2));
+  if (e == hipSuccess) e = hipMalloc((void**)&p->d_vgate, p->vgate_cap * sizeof(int2));
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->gate_done, hipEventDisableTiming);
   if (e != hipSuccess) {
     rc = e == hipErrorOutOfMemory ? XENG_ENOMEM : XENG_EHIP;
@@ -259,7 +319,7 @@ int xeng_plan_set_delays(xeng_plan_t p, const int32_t* delays, int D_max) {
     return XENG_OK;
   }
   const int N = p->N, nseg = (N + 15) / 16, nt = (N + kTile - 1) / kTile;
-  if (D_max < 0 || (long long)(D_max + 64) * p->F * N >= (1LL << 31)) return XENG_EINVAL;
+  if (D_max < 0 || ((long long)D_max + 64) * p->F * N >= (1LL << 31)) return XENG_EINVAL;
   std::vector<int> seg(nseg), blk(nt, 0);
   for (int n = 0; n < N; ++n) {
     if (delays[n] < 0 || delays[n] > D_max) return XENG_EINVAL;
@@ -273,8 +333,8 @@ int xeng_plan_set_delays(xeng_plan_t p, const int32_t* delays, int D_max) {
   // loads; otherwise the frame is copied, shifted, into plan-owned memory.
   bool fine = false;
   for (int k = 0; k < nseg; ++k) fine |= seg[k] != blk[(16 * k) / kTile];
-  // calls of this plan still in flight on any stream read the old delays
-  hipError_t e = p->shift ? hipDeviceSynchronize() : hipSuccess;
+  // the plan's last call may still read the old delays
+  hipError_t e = wait_tables(p);
   if (e == hipSuccess && fine && !p->d_shifted)
     e = hipMalloc((void**)&p->d_shifted, (size_t)p->T_max * p->F * N);
   if (e == hipSuccess && !p->d_seg_delay) e = hipMalloc((void**)&p->d_seg_delay, nseg * sizeof(int));
@@ -398,7 +458,7 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
     hipError_t e = wide ? xeng::launch_wide(a, p->form, s) : xeng::launch_tiles(a, p->form, aligned, s);
     if (e != hipSuccess) return hip_fail(p, e, "correlation kernel launch");
   }
-  return XENG_OK;
+  return p->shift ? mark_tables(p, s) : XENG_OK;
 }
 
 int xeng_correlate_gated(xeng_plan_t p, const uint8_t* samples, int N, int F, int T,
@@ -416,15 +476,28 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t* samples, int N, int F, in
     if (e != hipSuccess) return hip_fail(p, e, "hipEventSynchronize");
     p->gate_pending = false;
   }
-  // Runs of equal gate per launch segment, grouped by gate in time order:
-  // segment k's gate g owns runs h_gate_off[k (G + 1) + g] .. [.. + g + 1].
+  // Runs of equal gate per launch segment, grouped by gate in time order,
+  // then cut into work gates.  A run is integrated in whole chunks of kChunk
+  // samples, and the sums of codes are exact only while a work item
+  // integrates at most `seg` chunk-rounded samples.  Runs of 64 samples or
+  // more never exceed that (a segment holds at most `seg` samples), but a gate
+  // with many shorter runs can: its runs are then split, greedily in time
+  // order, into groups that fit, each its own work gate adding into the
+  // gate's buffer with int32 atomics (cleared first when the call
+  // overwrites).  Two consecutive groups of a gate hold more than `seg`
+  // chunk-rounded samples, and a segment holds at most 64 seg of them, so a
+  // segment has fewer than kSplitMax extra work gates.
   const int seg = segment_max(p->form);
   const int nseg = (T + seg - 1) / seg;
-  long long nruns = 0;
-  std::vector<int> count(G);
+  long long nruns = 0, ngoff = 0, nvg = 0;
+  int* count = p->gate_count.data();
+  int* fill = p->gate_fill.data();
+  int* zero = p->gate_zero.data();
+  std::fill(zero, zero + G, 0);
   for (int k = 0; k < nseg; ++k) {
     const int t0 = k * seg, t1 = std::min(T, t0 + seg);
-    std::fill(count.begin(), count.end(), 0);
+    const int mode = (p->accumulate || k > 0) ? xeng::WM_ADD : xeng::WM_STORE;
+    std::fill(count, count + G, 0);
     for (int t = t0; t < t1;) {  // count the runs of each gate
       const int g = gate[t];
       int u = t + 1;
@@ -432,25 +505,54 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t* samples, int N, int F, in
       if (g >= 0 && g < G) ++count[g];
       t = u;
     }
-    int* off = p->h_gate_off + (long long)k * (G + 1);
-    off[0] = (int)nruns;
-    for (int g = 0; g < G; ++g) off[g + 1] = off[g] + count[g];
-    std::vector<int> fill(off, off + G);
-    for (int t = t0; t < t1;) {  // and place them, in time order per gate
+    fill[0] = (int)nruns;
+    for (int g = 1; g < G; ++g) fill[g] = fill[g - 1] + count[g - 1];
+    for (int t = t0; t < t1;) {  // place them, in time order per gate
       const int g = gate[t];
       int u = t + 1;
       while (u < t1 && gate[u] == g) ++u;
       if (g >= 0 && g < G) p->h_runs[fill[g]++] = make_int2(t, u);
       t = u;
     }
-    nruns = off[G];
+    // work gates: fill[g] now ends gate g's runs
+    p->seg_goff[k] = (int)ngoff;
+    const long long vg0 = nvg;
+    int r = (int)nruns;
+    for (int g = 0; g < G; ++g) {
+      const int r_end = fill[g];
+      const long long first = nvg;
+      int b = r;
+      long long padded = 0;
+      for (int e = r; e < r_end; ++e) {
+        const int2 run = p->h_runs[e];
+        const long long pl = (long long)(run.y - run.x + kChunk - 1) / kChunk * kChunk;
+        if (e > b && padded + pl > seg) {
+          p->h_gate_off[ngoff++] = b;
+          p->h_vgate[nvg++] = make_int2(g, xeng::WM_ATOMIC);
+          b = e;
+          padded = 0;
+        }
+        padded += pl;
+      }
+      const bool split = nvg > first;
+      p->h_gate_off[ngoff++] = b;
+      p->h_vgate[nvg++] = make_int2(g, split ? xeng::WM_ATOMIC : mode);
+      if (split && mode == xeng::WM_STORE) zero[g] = 1;
+      r = r_end;
+    }
+    p->h_gate_off[ngoff++] = r;
+    nruns = r;
+    p->seg_nvg[k] = (int)(nvg - vg0);
   }
   hipError_t e = hipSuccess;
   if (nruns > 0)
     e = hipMemcpyAsync(p->d_runs, p->h_runs, nruns * sizeof(int2), hipMemcpyHostToDevice, s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(p->d_gate_off, p->h_gate_off, (size_t)nseg * (G + 1) * sizeof(int),
+    e = hipMemcpyAsync(p->d_gate_off, p->h_gate_off, (size_t)ngoff * sizeof(int),
                        hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->d_vgate, p->h_vgate, (size_t)nvg * sizeof(int2), hipMemcpyHostToDevice,
+                       s);
   if (e == hipSuccess) e = hipEventRecord(p->gate_done, s);
   if (e != hipSuccess) return hip_fail(p, e, "gate table upload");
   p->gate_pending = true;
@@ -463,26 +565,42 @@ int xeng_correlate_gated(xeng_plan_t p, const uint8_t* samples, int N, int F, in
   }
   const bool aligned = (N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples) & 15) == 0) &&
                        ((long long)F * N <= (1LL << 25));
+  // split gates that overwrite: their buffers are cleared first (the buffers
+  // of consecutive gates are contiguous in the gate-major output)
+  const long long gate_words = (long long)F * N * (N + 1);
+  for (int g = 0; g < G;) {
+    if (!zero[g]) {
+      ++g;
+      continue;
+    }
+    int h = g;
+    while (h < G && zero[h]) ++h;
+    e = xeng::launch_zero(vis + g * gate_words, (h - g) * gate_words, s);
+    if (e != hipSuccess) return hip_fail(p, e, "gate clear launch");
+    g = h;
+  }
   for (int k = 0; k < nseg; ++k) {
     xeng::GatedArgs a;
     a.samples = samples;
     a.vis = vis;
     a.N = N;
     a.F = F;
-    a.G = G;
+    a.G = p->seg_nvg[k];
     a.nt = (N + kTile - 1) / kTile;
     a.tiles_per_chan = (int)tiles_per_channel(N);
     a.write_mode = (p->accumulate || k > 0) ? xeng::WM_ADD : xeng::WM_STORE;
-    a.gate_off = p->d_gate_off + (long long)k * (G + 1);
+    a.gate_off = p->d_gate_off + p->seg_goff[k];
     a.runs = p->d_runs;
+    a.vgate = p->d_vgate + (p->seg_goff[k] - k);
     a.row_stride = (long long)F * N;
     a.seg_delay = kshift ? p->d_seg_delay : nullptr;
     a.blk_delay = kshift ? p->d_blk_delay : nullptr;
-    a.skip_empty = 0;
+    // adding: a work gate without runs adds nothing
+    a.skip_empty = a.write_mode == xeng::WM_ADD ? 1 : 0;
     e = xeng::launch_gated(a, p->form, aligned, s);
     if (e != hipSuccess) return hip_fail(p, e, "gated correlation kernel launch");
   }
-  return XENG_OK;
+  return p->shift ? mark_tables(p, s) : XENG_OK;
 }
 
 // Event rows a frame of T samples can need per channel: a block of rows never
@@ -561,6 +679,7 @@ int xeng_correlate_flagged(xeng_plan_t p, uint8_t* samples, const uint32_t* flag
     g.row_stride = (long long)F * N;
     g.seg_delay = nullptr;
     g.blk_delay = nullptr;
+    g.vgate = nullptr;
     g.skip_empty = 1;
     e = xeng::launch_gated(g, XENG_FORM_I8, aligned, s);
     if (e != hipSuccess) return hip_fail(p, e, "event correlation kernel launch");
@@ -646,8 +765,8 @@ int xeng_beam_set_weights(xeng_plan_t p, const int8_t* weights) {
               corr[(size_t)f * NBT * 32 + col] += 8 * (cr + ci);
             }
           }
-  // calls of this plan still in flight on any stream read the old operands
-  hipError_t e = hipDeviceSynchronize();
+  // the plan's last call may still read the old operands
+  hipError_t e = wait_tables(p);
   if (e == hipSuccess) e = hipMemcpy(p->d_wop, wop.data(), wop.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(p->d_bcorr, corr.data(), corr.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -684,7 +803,7 @@ int xeng_beamform(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, in
       if (e != hipSuccess) return hip_fail(p, e, "beamform kernel launch");
     }
   }
-  return XENG_OK;
+  return mark_tables(p, s);
 }
 
 int xeng_plan_batch(xeng_plan_t* out, const xeng_instance* descs, int count, unsigned flags) {
@@ -720,15 +839,8 @@ int xeng_plan_batch(xeng_plan_t* out, const xeng_instance* descs, int count, uns
     for (int k = 0; k < count; ++k) {
       const xeng_instance& d = descs[k];
       const int nt = (d.N + kTile - 1) / kTile;
-      int S = d.split_t > 0 ? d.split_t : std::max(1, std::min(s_auto, d.T / 1024));
-      // no slice may integrate more than XENG_F8_FLUSH_MAX (FP8) or
-      // XENG_I8_SEG_MAX (int8) samples
-      const int seg_max = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : XENG_I8_SEG_MAX;
-      S = std::max(S, (d.T + seg_max - 1) / seg_max);
-      S = std::min(S, (d.T + kChunk - 1) / kChunk);
-      int len = (d.T + S - 1) / S;
-      len = (len + kChunk - 1) / kChunk * kChunk;
-      S = (d.T + len - 1) / len;
+      int S = 0, len = 0;
+      batch_slices(d, s_auto, p->form, S, len);
       const int mode = (S > 1 || shared) ? xeng::WM_ATOMIC
                                          : (p->accumulate ? xeng::WM_ADD : xeng::WM_STORE);
       if (S > 1 && !p->accumulate) {
@@ -914,6 +1026,8 @@ int xeng_destroy(xeng_plan_t p) {
   if (p->d_runs) (void)hipFree(p->d_runs);
   if (p->h_gate_off) (void)hipHostFree(p->h_gate_off);
   if (p->h_runs) (void)hipHostFree(p->h_runs);
+  if (p->d_vgate) (void)hipFree(p->d_vgate);
+  if (p->h_vgate) (void)hipHostFree(p->h_vgate);
   if (p->d_seg_delay) (void)hipFree(p->d_seg_delay);
   if (p->d_blk_delay) (void)hipFree(p->d_blk_delay);
   if (p->d_shifted) (void)hipFree(p->d_shifted);
@@ -923,6 +1037,7 @@ int xeng_destroy(xeng_plan_t p) {
   if (p->d_fruns) (void)hipFree(p->d_fruns);
   if (p->d_wop) (void)hipFree(p->d_wop);
   if (p->d_bcorr) (void)hipFree(p->d_bcorr);
+  if (p->tables_used) (void)hipEventDestroy(p->tables_used);
   delete p;
   return XENG_OK;
 }

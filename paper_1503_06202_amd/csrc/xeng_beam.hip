@@ -191,6 +191,9 @@ hipError_t launch_aligned_or_not(const BeamArgs& a, bool aligned, hipStream_t st
 int beam_rows_per_block(int nb, bool aligned) { return 4 * 32 * tt_of(nb, aligned); }
 
 hipError_t launch_beams(BeamArgs a, int nb, bool aligned, hipStream_t stream) {
+  // a launch reads the weight operands and offset terms of component tiles
+  // c0 .. c0 + nb - 1, which must lie inside the NBT tiles the plan holds
+  if (nb < 1 || nb > 4 || a.c0 < 0 || a.c0 + nb > a.NBT) return hipErrorInvalidValue;
   const int rows = beam_rows_per_block(nb, aligned);
   a.tblocks = (a.T + rows - 1) / rows;
   switch (nb) {

@@ -38,17 +38,22 @@ struct TileArgs {
 
 hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t stream);
 
-// Output gating: every (channel, tile, gate) integrates the runs of its gate,
-// runs[gate_off[g] .. gate_off[g + 1]) (absolute [begin, end) sample ranges),
-// into vis + g * F * N(N+1) (gate-major output [G][F][N(N+1)/2][2]).
+// Output gating: every (channel, tile, work gate g) integrates the runs
+// runs[gate_off[g] .. gate_off[g + 1]) (absolute [begin, end) sample ranges)
+// into the buffer vis + og * F * N(N+1) (gate-major output [G][F][N(N+1)/2][2]).
+// Without vgate, work gate g is output gate og = g, written in write_mode.
+// With vgate, vgate[g] = (og, mode): a gate whose runs, each integrated in
+// whole chunks, hold more samples than one exact integration may is split
+// into several work gates that add into its buffer with int32 atomics.
 struct GatedArgs {
   const uint8_t* samples;
   int32_t* vis;
-  int N, F, G;
+  int N, F, G;            // G: work gates of this launch
   int nt, tiles_per_chan;
   int write_mode;         // WM_STORE or WM_ADD (one work item per output tile)
   const int* gate_off;    // device [G + 1]
   const int2* runs;       // device [gate_off[G]]
+  const int2* vgate;      // device [G] (output gate, write mode), or NULL
   long long row_stride;
   const int* seg_delay;   // time shifting, as in TileArgs
   const int* blk_delay;

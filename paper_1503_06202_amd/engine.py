@@ -277,6 +277,27 @@ def correlate(samples: torch.Tensor, form: str = "i8", vis: Optional[torch.Tenso
         return p.correlate(samples, vis, stream)
 
 
+def _pointer_arrays(instances, samples, vis):
+    """Device pointer arrays of a batch; a None sample tensor skips that instance."""
+    n = len(instances)
+    if len(samples) != n or len(vis) != n:
+        raise ValueError(f"need {n} sample and vis entries")
+    sp = (ctypes.c_void_p * max(1, n))()
+    vp = (ctypes.c_void_p * max(1, n))()
+    for k, (N, F, T) in enumerate(instances):
+        if samples[k] is None:
+            continue
+        Ts, Fs, Ns = _check_samples(samples[k])
+        if (Ts, Fs, Ns) != (T, F, N):
+            raise ValueError(f"instance {k}: samples shape {(Ts, Fs, Ns)} != planned {(T, F, N)}")
+        if vis[k] is None:
+            raise ValueError(f"instance {k} is active and needs its vis")
+        _check_vis(vis[k], N, F, samples[k].device)
+        sp[k] = samples[k].data_ptr()
+        vp[k] = vis[k].data_ptr()
+    return sp, vp
+
+
 class BatchPlan:
     """Many independent (N, F, T) instances correlated by one persistent launch."""
 
@@ -305,23 +326,7 @@ class BatchPlan:
     def _arrays(self, samples: Sequence[Optional[torch.Tensor]],
                 vis: Sequence[Optional[torch.Tensor]]):
         """Pointer arrays; a None sample tensor skips that instance this call."""
-        n = len(self.instances)
-        if len(samples) != n or len(vis) != n:
-            raise ValueError(f"need {n} sample and vis entries")
-        sp = (ctypes.c_void_p * n)()
-        vp = (ctypes.c_void_p * n)()
-        for k, (N, F, T) in enumerate(self.instances):
-            if samples[k] is None:
-                continue
-            Ts, Fs, Ns = _check_samples(samples[k])
-            if (Ts, Fs, Ns) != (T, F, N):
-                raise ValueError(f"instance {k}: samples shape {(Ts, Fs, Ns)} != planned {(T, F, N)}")
-            if vis[k] is None:
-                raise ValueError(f"instance {k} is active and needs its vis")
-            _check_vis(vis[k], N, F, samples[k].device)
-            sp[k] = samples[k].data_ptr()
-            vp[k] = vis[k].data_ptr()
-        return sp, vp
+        return _pointer_arrays(self.instances, samples, vis)
 
     def correlate(self, samples: Sequence[Optional[torch.Tensor]],
                   vis: Sequence[Optional[torch.Tensor]],
@@ -334,33 +339,6 @@ class BatchPlan:
         fn = _lib.lib().xeng_correlate_batch_graph if graph else _lib.lib().xeng_correlate_batch
         rc = fn(self._h, sp, vp, _stream_handle(stream))
         _lib.check(rc, "xeng_correlate_batch", self._h.value)
-
-    def set_weights(self, weights) -> None:
-        """Beam weights, int8 [F][B][N][2] (re, im) in -127..127, applied
-        without a conjugate (host array; copied to the device)."""
-        import numpy as np
-
-        w = np.ascontiguousarray(np.asarray(weights, dtype=np.int8))
-        if w.shape != (self.F, self.beams, self.N, 2):
-            raise ValueError(f"weights must be int8 {(self.F, self.beams, self.N, 2)}")
-        _lib.check(_lib.lib().xeng_beam_set_weights(
-            self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))), "xeng_beam_set_weights",
-            self._h.value)
-
-    def beamform(self, samples: torch.Tensor, out: Optional[torch.Tensor] = None,
-                 stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
-        """Beams int32 [T][F][B][2]: y = sum_n w[f][b][n] x[t][f][n]."""
-        T, F, N = _check_samples(samples)
-        shape = (T, F, self.beams, 2)
-        if out is None:
-            out = torch.empty(shape, dtype=torch.int32, device=samples.device)
-        elif (out.dtype != torch.int32 or tuple(out.shape) != shape or not out.is_cuda
-              or not out.is_contiguous() or out.device != samples.device):
-            raise ValueError(f"out must be a contiguous int32 {shape} tensor on the samples' GPU")
-        rc = _lib.lib().xeng_beamform(self._h, samples.data_ptr(), N, F, T, out.data_ptr(),
-                                      _stream_handle(stream))
-        _lib.check(rc, "xeng_beamform", self._h.value)
-        return out
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None and self._h.value:

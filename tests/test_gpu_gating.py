@@ -76,6 +76,24 @@ def test_gates_across_launch_segments(form, T, N):
     assert np.array_equal(gated(s, gate, 4, form), want(s, gate, 4))
 
 
+@pytest.mark.parametrize("form,T", [("f8", 32768 + 100), ("i8", (1 << 19) + 1000)])
+def test_per_sample_gates_long_frame(form, T):
+    # runs of one or two samples, each integrated as a whole chunk of 64: a
+    # gate holds far more chunk-rounded samples per launch segment than one
+    # exact integration may (32768 in FP8, 2^19 in int8), so it is split
+    # into work gates that add atomically; gate 2 has long runs only and is
+    # not split
+    N, F, G = 64, 2, 3
+    s = rand_frame(56, T, F, N)
+    gate = np.random.default_rng(57).integers(-1, 2, T).astype(np.int32)  # -1 drops
+    gate[(np.arange(T) // 1000) % 5 == 4] = 2
+    ref = want(s, gate, G)
+    print(f"per-sample gates form={form} T={T}", flush=True)
+    assert np.array_equal(gated(s, gate, G, form), ref)
+    vis = torch.from_numpy(np.full(ref.shape, -3, dtype=np.int32)).to(DEV)
+    assert np.array_equal(gated(s, gate, G, form, vis=vis, accumulate=True), ref - 3)
+
+
 def test_gates_sum_to_ungated():
     T, F, N, G = 4096 + 64, 8, 512, 6
     s = synth.gen_frame(N, F, T, 9, "gauss")
