@@ -57,7 +57,8 @@ enum {
     XENG_EPLAN = -2,     /* argument disagrees with the plan (N, F, T > T_max, count) */
     XENG_EOVERFLOW = -3, /* T > XENG_T_EXACT_MAX: int32 could overflow */
     XENG_EHIP = -4,      /* HIP runtime or launch error (text: xeng_plan_error) */
-    XENG_ENOMEM = -5     /* host or device workspace allocation failed */
+    XENG_ENOMEM = -5,    /* host or device workspace allocation failed */
+    XENG_ELIMIT = -6     /* request exceeds the fixed workspace of xeng_correlate_batch_noalloc */
 };
 
 /* Flags of xeng_plan / xeng_plan_batch. */
@@ -80,6 +81,8 @@ enum {
                                      (or per batch slice), at most; the int32 sums of codes
                                      then stay below 2^31.  Longer frames are split into
                                      launches that add in stream order (or into more slices). */
+#define XENG_NOALLOC_INST_MAX 64      /* xeng_correlate_batch_noalloc: active instances per call */
+#define XENG_NOALLOC_ITEMS_MAX 65536  /* xeng_correlate_batch_noalloc: work items per call */
 
 /* Library version: (major << 16) | minor. */
 int xeng_version(void);
@@ -319,6 +322,33 @@ int xeng_correlate_batch(xeng_plan_t p, const uint8_t *const *samples, int32_t *
  */
 int xeng_correlate_batch_graph(xeng_plan_t p, const uint8_t *const *samples,
                                int32_t *const *vis, void *stream);
+
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the batched form without a
+ * plan.  The result is that of xeng_plan_batch(descs, count, flags) followed
+ * by xeng_correlate_batch(samples, vis) on `stream`; instances with
+ * samples[k] == NULL are skipped.  The call only launches kernels: no
+ * allocation, no copy, no host synchronisation.  The instance table, the work
+ * list and the work counter live in the library's fixed device workspace, a
+ * file-scope array of about 2 MiB that each GPU the library runs on holds
+ * until the process ends; the call's first use on a device looks up its
+ * address there.  Every call on a GPU shares that GPU's workspace: calls that
+ * overlap on one GPU (on several streams, or from several threads) race, and
+ * the caller must order them (one stream, or events).
+ * Limits: at most XENG_NOALLOC_INST_MAX active instances and at most
+ * XENG_NOALLOC_ITEMS_MAX work items, the sum over active instances of
+ * F x nt (nt + 1) / 2 x (time slices), nt = ceil(N / 128).
+ * Errors: XENG_EINVAL (NULL arrays, count < 1, any N, F or T < 1, any
+ * N > XENG_N_MAX, negative split_t, unknown flags, XENG_SHARED_VIS without
+ * XENG_ACCUMULATE, NULL vis[k] of an active instance), XENG_EOVERFLOW (any
+ * T > XENG_T_EXACT_MAX), XENG_ELIMIT (a limit above is exceeded; nothing is
+ * queued), XENG_EHIP (a HIP runtime or launch error; with no plan, its text
+ * is not kept).
+ */
+int xeng_correlate_batch_noalloc(const xeng_instance *descs, int count, unsigned flags,
+                                 const uint8_t *const *samples, int32_t *const *vis,
+                                 void *stream);
 
 #ifdef __cplusplus
 }

@@ -16,6 +16,7 @@ XENG_EPLAN = -2
 XENG_EOVERFLOW = -3
 XENG_EHIP = -4
 XENG_ENOMEM = -5
+XENG_ELIMIT = -6
 
 XENG_FORM_I8 = 0
 XENG_FORM_F8 = 1
@@ -28,6 +29,8 @@ XENG_BEAMS_MAX = 1024
 XENG_F8_FLUSH_MAX = 32768
 XENG_I8_SEG_MAX = 524288
 XENG_G_MAX = 65536
+XENG_NOALLOC_INST_MAX = 64
+XENG_NOALLOC_ITEMS_MAX = 65536
 
 # every symbol include/xeng.h declares
 EXPORTS = (
@@ -35,7 +38,7 @@ EXPORTS = (
     "xeng_destroy", "xeng_plan_error", "xeng_plan_batch", "xeng_correlate_batch",
     "xeng_correlate_batch_graph", "xeng_plan_gated", "xeng_correlate_gated",
     "xeng_plan_set_delays", "xeng_plan_flagged", "xeng_correlate_flagged", "xeng_normalize",
-    "xeng_plan_beams", "xeng_beam_set_weights", "xeng_beamform",
+    "xeng_plan_beams", "xeng_beam_set_weights", "xeng_beamform", "xeng_correlate_batch_noalloc",
 )
 
 
@@ -98,6 +101,9 @@ def lib() -> ctypes.CDLL:
     L.xeng_beam_set_weights.restype = ci
     L.xeng_beamform.argtypes = [vp, vp, ci, ci, ci, vp, vp]
     L.xeng_beamform.restype = ci
+    L.xeng_correlate_batch_noalloc.argtypes = [ctypes.POINTER(XengInstance), ci, ctypes.c_uint,
+                                               ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
+    L.xeng_correlate_batch_noalloc.restype = ci
     _lib = L
     return L
 

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "xeng_internal.hpp"
+#include "xeng_noalloc.hpp"
 
 namespace {
 
@@ -245,6 +246,7 @@ const char* xeng_strerror(int code) {
     case XENG_EOVERFLOW: return "integration too long for exact int32 sums";
     case XENG_EHIP: return "HIP runtime or launch error";
     case XENG_ENOMEM: return "out of memory";
+    case XENG_ELIMIT: return "request exceeds the fixed workspace of the allocation-free entry point";
     default: return "unknown error code";
   }
 }
@@ -1009,6 +1011,104 @@ int xeng_correlate_batch_graph(xeng_plan_t p, const uint8_t* const* samples,
   }
   hipError_t e = hipGraphLaunch(p->graph_exec, s);
   if (e != hipSuccess) return hip_fail(p, e, "hipGraphLaunch");
+  return XENG_OK;
+}
+
+int xeng_correlate_batch_noalloc(const xeng_instance* descs, int count, unsigned flags,
+                                 const uint8_t* const* samples, int32_t* const* vis,
+                                 void* stream) {
+  if (!descs || !samples || !vis || count < 1 || !flags_ok(flags, true)) return XENG_EINVAL;
+  int active = 0;
+  for (int k = 0; k < count; ++k) {
+    const xeng_instance& d = descs[k];
+    if (d.N < 1 || d.F < 1 || d.T < 1 || d.N > XENG_N_MAX || d.split_t < 0) return XENG_EINVAL;
+    if (samples[k] && !vis[k]) return XENG_EINVAL;
+    active += samples[k] ? 1 : 0;
+  }
+  for (int k = 0; k < count; ++k)
+    if (descs[k].T > XENG_T_EXACT_MAX) return XENG_EOVERFLOW;
+  if (active > XENG_NOALLOC_INST_MAX) return XENG_ELIMIT;
+  // every tile takes at least one work item
+  long long tiles = 0;
+  for (int k = 0; k < count; ++k)
+    if (samples[k]) tiles += descs[k].F * tiles_per_channel(descs[k].N);
+  if (tiles > XENG_NOALLOC_ITEMS_MAX) return XENG_ELIMIT;
+  if (active == 0) return XENG_OK;
+
+  unsigned char* ws = nullptr;
+  int cus = 0;
+  if (xeng::noalloc_workspace(&ws, &cus) != hipSuccess) {
+    (void)hipGetLastError();
+    return XENG_EHIP;
+  }
+  const int form = (int)(flags & XENG_FORM_MASK);
+  const bool accumulate = (flags & XENG_ACCUMULATE) != 0;
+  const bool shared = (flags & XENG_SHARED_VIS) != 0;
+  // the same schedule rules as xeng_plan_batch, over the active instances;
+  // instances go in decreasing order of their largest work item, so that
+  // the longest items start first
+  const int s_auto = auto_slices(tiles, XENG_T_EXACT_MAX, cus);
+  xeng::NoallocArgs a;
+  long long cost[XENG_NOALLOC_INST_MAX];
+  int order[XENG_NOALLOC_INST_MAX];
+  int n = 0;
+  long long nitems = 0;
+  bool any_zero = false;
+  for (int k = 0; k < count; ++k) {
+    if (!samples[k]) continue;
+    const xeng_instance& d = descs[k];
+    xeng::NoallocInst& in = a.inst[n];
+    int S = 0, len = 0;
+    batch_slices(d, s_auto, form, S, len);
+    const int mode = (S > 1 || shared) ? xeng::WM_ATOMIC
+                                       : (accumulate ? xeng::WM_ADD : xeng::WM_STORE);
+    const bool zero = S > 1 && !accumulate;
+    const bool aligned = (d.N % 16 == 0) && ((reinterpret_cast<uintptr_t>(samples[k]) & 15) == 0) &&
+                         ((long long)d.F * d.N <= (1LL << 25));
+    in.samples = samples[k];
+    in.vis = vis[k];
+    in.N = d.N;
+    in.F = d.F;
+    in.T = d.T;
+    in.S = S;
+    in.len = len;
+    in.flags = mode | (zero ? 4 : 0) | (aligned ? 8 : 0);
+    in.first = 0;
+    in.pad = 0;
+    any_zero |= zero;
+    nitems += (long long)d.F * tiles_per_channel(d.N) * S;
+    const long long edge = std::min(kTile, d.N);
+    cost[n] = edge * edge * len;
+    order[n] = n;
+    ++n;
+  }
+  if (nitems > XENG_NOALLOC_ITEMS_MAX) return XENG_ELIMIT;
+  for (int i = 1; i < n; ++i)  // insertion sort by decreasing cost (stable)
+    for (int j = i; j > 0 && cost[order[j]] > cost[order[j - 1]]; --j)
+      std::swap(order[j], order[j - 1]);
+  xeng::NoallocInst sorted[XENG_NOALLOC_INST_MAX];
+  int first = 0;
+  for (int i = 0; i < n; ++i) {
+    sorted[i] = a.inst[order[i]];
+    sorted[i].first = first;
+    first += sorted[i].F * (int)tiles_per_channel(sorted[i].N) * sorted[i].S;
+  }
+  std::copy(sorted, sorted + n, a.inst);
+  a.ws = ws;
+  a.ninst = n;
+  a.nitems = (int)nitems;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = xeng::launch_noalloc_prep(a, s);
+  if (e == hipSuccess) {
+    const int grid = (int)std::max(1LL, std::min<long long>((long long)cus * kOccupancy, nitems));
+    e = xeng::launch_batch(reinterpret_cast<const xeng::BatchInst*>(ws + xeng::kNoallocInstOff),
+                           n, reinterpret_cast<const xeng::BatchItem*>(ws + xeng::kNoallocItemsOff),
+                           (int)nitems, reinterpret_cast<int*>(ws), grid, form, any_zero, s);
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return XENG_EHIP;
+  }
   return XENG_OK;
 }
 

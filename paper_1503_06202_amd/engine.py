@@ -277,6 +277,35 @@ def correlate(samples: torch.Tensor, form: str = "i8", vis: Optional[torch.Tenso
         return p.correlate(samples, vis, stream)
 
 
+def correlate_batch_noalloc(instances: Sequence[Tuple[int, int, int]],
+                            samples: Sequence[Optional[torch.Tensor]],
+                            vis: Sequence[Optional[torch.Tensor]], form: str = "i8",
+                            accumulate: bool = False, split_t: Optional[Sequence[int]] = None,
+                            shared_vis: bool = False,
+                            stream: Optional[torch.cuda.Stream] = None) -> None:
+    """The batched form without a plan (``xeng_correlate_batch_noalloc``): the
+    library allocates nothing and queues kernels only, for callers that cannot
+    allocate.  Calls that overlap on one GPU share its fixed workspace and
+    race: keep them on one stream."""
+    if form not in FORMS:
+        raise ValueError(f"form must be one of {sorted(FORMS)}")
+    inst = [tuple(map(int, x)) for x in instances]
+    n = len(inst)
+    splits = list(split_t) if split_t is not None else [0] * n
+    if len(splits) != n:
+        raise ValueError("one split_t per instance")
+    arr = (_lib.XengInstance * max(1, n))()
+    for k, ((N, F, T), sp) in enumerate(zip(inst, splits)):
+        arr[k] = _lib.XengInstance(N, F, T, int(sp))
+    sp_arr, vp_arr = _pointer_arrays(inst, samples, vis)
+    flags = FORMS[form] | (_lib.XENG_ACCUMULATE if accumulate else 0)
+    if shared_vis:
+        flags |= _lib.XENG_SHARED_VIS
+    rc = _lib.lib().xeng_correlate_batch_noalloc(arr, n, flags, sp_arr, vp_arr,
+                                                 _stream_handle(stream))
+    _lib.check(rc, "xeng_correlate_batch_noalloc")
+
+
 def _pointer_arrays(instances, samples, vis):
     """Device pointer arrays of a batch; a None sample tensor skips that instance."""
     n = len(instances)

@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(L):
 
 def test_version_and_strerror(L):
     assert L.xeng_version() >> 16 == 1
-    for code in (0, -1, -2, -3, -4, -5):
+    for code in (0, -1, -2, -3, -4, -5, -6):
         assert L.xeng_strerror(code)
     assert L.xeng_strerror(-99) == b"unknown error code"
 
@@ -236,3 +236,32 @@ def test_python_layer_rejects_cpu_tensors():
         engine._check_samples(torch.zeros((4, 1, 8), dtype=torch.uint8))
     with pytest.raises(ValueError):
         engine._check_samples(torch.zeros((4, 8), dtype=torch.uint8))
+
+
+def test_noalloc_batch_validation_needs_no_gpu(L):
+    # argument errors and the fixed workspace's limits are decided on the host
+    # before any HIP call
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced
+    n = _lib.XENG_NOALLOC_INST_MAX + 1
+    inst = (_lib.XengInstance * n)(*[_lib.XengInstance(16, 1, 64, 0)] * n)
+    sp = (ctypes.c_void_p * n)(*[dummy] * n)
+    vp = (ctypes.c_void_p * n)(*[dummy] * n)
+    f = L.xeng_correlate_batch_noalloc
+    assert f(None, 1, 0, sp, vp, None) == _lib.XENG_EINVAL
+    assert f(inst, 0, 0, sp, vp, None) == _lib.XENG_EINVAL
+    assert f(inst, 1, 0, None, vp, None) == _lib.XENG_EINVAL
+    assert f(inst, 1, 0x400, sp, vp, None) == _lib.XENG_EINVAL
+    assert f(inst, 1, _lib.XENG_SHARED_VIS, sp, vp, None) == _lib.XENG_EINVAL
+    assert f(inst, n, 0, sp, vp, None) == _lib.XENG_ELIMIT
+    bad = (_lib.XengInstance * 1)(_lib.XengInstance(16, 1, 64, -1))
+    assert f(bad, 1, 0, sp, vp, None) == _lib.XENG_EINVAL
+    big = (_lib.XengInstance * 1)(_lib.XengInstance(16, 1, _lib.XENG_T_EXACT_MAX + 1, 0))
+    sp2 = (ctypes.c_void_p * 1)(dummy)
+    vp2 = (ctypes.c_void_p * 1)(dummy)
+    assert f(big, 1, 0, sp2, vp2, None) == _lib.XENG_EOVERFLOW
+    # N = 32768: 32896 tiles per channel, so two channels are more work items
+    # than the workspace holds
+    many = (_lib.XengInstance * 1)(_lib.XengInstance(_lib.XENG_N_MAX, 2, 64, 0))
+    assert f(many, 1, 0, sp2, vp2, None) == _lib.XENG_ELIMIT
+    vnull = (ctypes.c_void_p * 1)()
+    assert f(many, 1, 0, sp2, vnull, None) == _lib.XENG_EINVAL
