@@ -10,6 +10,8 @@
 // described in xcorr_tile.hpp.
 #pragma once
 
+#include <type_traits>
+
 #include "xcorr_tile.hpp"
 #include "xeng_internal.hpp"
 
@@ -45,19 +47,25 @@ struct StageRole {
 // Time shifting: the I and J pieces are read `shiftI` / `shiftJ` bytes (the
 // largest delay of the block, in rows) before `rows`, and a lane's offset
 // adds back its own segment's rows (see tile_body).
+//
+// NP: pieces per thread, 4 (I and J blocks) or 2 (the I block alone, for a
+// diagonal tile, whose J block is the same rows).
+template <int NP>
 __device__ __forceinline__ void load_pieces_fast(v4i (&raw)[4], const uint8_t* __restrict__ rows,
                                                  long long row_stride, uint32_t offI,
                                                  uint32_t offJ, long long shiftI = 0,
                                                  long long shiftJ = 0) {
   const __amdgpu_buffer_rsrc_t rI =
       __builtin_amdgcn_make_buffer_rsrc((void*)(rows - shiftI), (short)0, 0x7fffffff, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rJ =
-      __builtin_amdgcn_make_buffer_rsrc((void*)(rows - shiftJ), (short)0, 0x7fffffff, 0x00020000);
   const int s16 = (int)(16 * row_stride);
   raw[0] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rI, (int)offI, 0, 0));
   raw[1] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rI, (int)offI, s16, 0));
-  raw[2] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rJ, (int)offJ, 0, 0));
-  raw[3] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rJ, (int)offJ, s16, 0));
+  if (NP == 4) {
+    const __amdgpu_buffer_rsrc_t rJ = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(rows - shiftJ), (short)0, 0x7fffffff, 0x00020000);
+    raw[2] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rJ, (int)offJ, 0, 0));
+    raw[3] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rJ, (int)offJ, s16, 0));
+  }
 }
 
 // General path (frame edges, unaligned rows, ragged tails): byte loads of the
@@ -81,16 +89,19 @@ __device__ __forceinline__ v4i load_piece_edge(const uint8_t* __restrict__ sampl
   return v4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
 }
 
-// The four pieces of a thread by the general path; t_chunk is the chunk's
-// first time.
+// The pieces of a thread (NP as in load_pieces_fast) by the general path;
+// t_chunk is the chunk's first time.
+template <int NP>
 __device__ __forceinline__ void load_pieces_edge(v4i (&raw)[4], const uint8_t* __restrict__ samples,
                                                  long long row_stride, int f, int N, int nI,
                                                  int nJ, const StageRole& sr, int t_chunk,
                                                  int t_end, int dI = 0, int dJ = 0) {
   raw[0] = load_piece_edge(samples, row_stride, f, N, nI, t_chunk + sr.rI, t_end, dI);
   raw[1] = load_piece_edge(samples, row_stride, f, N, nI, t_chunk + sr.rI + 16, t_end, dI);
-  raw[2] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ, t_end, dJ);
-  raw[3] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ + 16, t_end, dJ);
+  if (NP == 4) {
+    raw[2] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ, t_end, dJ);
+    raw[3] = load_piece_edge(samples, row_stride, f, N, nJ, t_chunk + sr.rJ + 16, t_end, dJ);
+  }
 }
 
 // Store a piece, unchanged, into the LDS plane of its block (rows = times, as
@@ -120,10 +131,11 @@ __device__ __forceinline__ void stage_piece_k(const v4i& raw, int k, uint8_t* __
     stage_piece(raw, stage + BLOCK_LDS + (sr.rJ + 16 * (k - 2)) * PROW + 16 * sr.seg);
 }
 
+template <int NP>
 __device__ __forceinline__ void stage_pieces(const v4i (&raw)[4], uint8_t* __restrict__ stage,
                                              const StageRole& sr) {
 #pragma unroll
-  for (int k = 0; k < 4; ++k) stage_piece_k(raw[k], k, stage, sr);
+  for (int k = 0; k < NP; ++k) stage_piece_k(raw[k], k, stage, sr);
 }
 
 template <int FORM>
@@ -181,16 +193,33 @@ __device__ __forceinline__ uint32_t badd(int x, int y, uint32_t acc) {
 // FP8 operand scale: e8m0 exponent 127 + 9, i.e. 2^9 (code u reads u * 2^-9).
 constexpr int F8_SCALE = 127 + 9;
 
+// What one wave does in a tile's chunk loop.  Every field is a compile-time
+// constant, so that the loops stay straight-line code.
+//   SA, SB  the A and B fragment (0 or 1) whose codes the wave sums (-1: none)
+//   KPAR    the k-steps it computes: 0 all; 1 the even and 2 the odd ones (two
+//           waves share one 64 x 64 sub-tile of a diagonal tile)
+//   SKIP10  no MFMAs for block (a = 1, b = 0), which lies below the diagonal
+//           in a sub-tile on the diagonal
+//   DIAG    a diagonal tile (I == J): only the I block is staged, and the B
+//           fragments are read from it too
+//   COMPUTE issue MFMAs (false: a wave whose sub-tile lies below the diagonal
+//           only sums its fragments)
+template <int SA_, int SB_, int KPAR_, bool SKIP10_, bool DIAG_, bool COMPUTE_ = true>
+struct Role {
+  static constexpr int SA = SA_, SB = SB_, KPAR = KPAR_;
+  static constexpr bool SKIP10 = SKIP10_, DIAG = DIAG_, COMPUTE = COMPUTE_;
+  static constexpr bool SUMS = SA_ >= 0 || SB_ >= 0;
+  static constexpr int NP = DIAG_ ? 2 : 4;  // pieces a thread loads and stages per chunk
+};
+
 // One chunk for a wave's 64 x 64 sub-tile (2 x 2 blocks of 32 x 32).
 // lds: the chunk's stage (I block at 0, J block at BLOCK_LDS); lane_rd: this
 // lane's transpose-read offset within a k-step (its row group and column);
 // rowA / rowB: the wave's first input row within the I and J blocks.
 //
-// COMPUTE: issue the MFMAs (a wave whose blocks all lie below the diagonal
-// only sums its fragments).  SA / SB: the A and B fragment this wave sums.
-// STAGE: the pieces `stg` of the next chunk are staged into the stage at `blk`
-// between the k-steps (one piece per int8 k-step, two per FP8 k-step), so
-// that the staging arithmetic issues while the matrix cores work.
+// R: the wave's role (see Role).  STAGE: the pieces `stg` of the next chunk
+// are staged into the stage at `blk` between the k-steps (spread evenly over
+// them), so that the staging issues while the matrix cores work.
 //
 // Operands.  Int8: a lane's 16 bytes pack [m(8), r(8)] for 8 samples; Re =
 // A.B and Im = A.Y with Y = [r(8), 15 - m(8)] (15 - m = m ^ 15 per byte, one
@@ -200,28 +229,24 @@ constexpr int F8_SCALE = 127 + 9;
 // the power limit.  Y is B's registers shifted by two, with 15 - m appended.
 // FP8: a lane's 32 bytes pack [r(8), m(8), r(8), m(8)] for 16 samples; Y =
 // [-m, r, -m, r], the negation flipping the sign bit.
-//
-// SA = SB = -1: the fragments to sum are chosen at run time (sa, sb), all
-// four fragments are read, and the MFMAs run only when `mfma` is set.
-template <int FORM, bool COMPUTE, bool STAGE, int SA, int SB>
+template <int FORM, class R, bool STAGE>
 __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, int lane_rd,
                                               int rowA, int rowB,
                                               typename Acc<FORM>::T (&re)[2][2],
                                               typename Acc<FORM>::T (&im)[2][2], TileSums& sm,
                                               const v4i* stg = nullptr, uint8_t* blk = nullptr,
-                                              const StageRole* sr = nullptr, int sa = 0,
-                                              int sb = 0, bool mfma = true) {
-  constexpr bool RT = SA < 0;
+                                              const StageRole* sr = nullptr) {
   const uint8_t* pa = lds + lane_rd + rowA;
-  const uint8_t* pb = lds + BLOCK_LDS + lane_rd + rowB;
+  const uint8_t* pb = lds + (R::DIAG ? 0 : BLOCK_LDS) + lane_rd + rowB;
   if (FORM == FORM_I8) {
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
+      const bool kon = R::COMPUTE && (R::KPAR == 0 || (s & 1) == R::KPAR - 1);
       v4i A[2], B[2], Y[2];
       v2i ar[2], am[2], br[2], bm[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        if (!COMPUTE && !RT && a != SA) continue;
+        if (!kon && a != R::SA) continue;
         const v2i w = lds_tr8(pa + 16 * s * PROW + 32 * a);
         ar[a] = hi_codes(w);
         am[a] = lo_codes(w);
@@ -229,7 +254,7 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        if (!COMPUTE && !RT && b != SB) continue;
+        if (!kon && b != R::SB) continue;
         const v2i wb = lds_tr8(pb + 16 * s * PROW + 32 * b);
         br[b] = hi_codes(wb);
         bm[b] = lo_codes(wb);
@@ -238,33 +263,40 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
         B[b] = __builtin_shufflevector(w, w, 0, 1, 2, 3);
         Y[b] = __builtin_shufflevector(w, w, 2, 3, 4, 5);
       }
-      if (COMPUTE && (!RT || mfma)) {
+      if (kon) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
+            if (R::SKIP10 && a == 1 && b == 0) continue;
             re[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], B[b], re[a][b], 0, 0, 0);
             im[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], Y[b], im[a][b], 0, 0, 0);
           }
       }
-      const v2i sar = RT ? (sa ? ar[1] : ar[0]) : ar[RT ? 0 : SA];
-      const v2i sam = RT ? (sa ? am[1] : am[0]) : am[RT ? 0 : SA];
-      const v2i sbr = RT ? (sb ? br[1] : br[0]) : br[RT ? 0 : SB];
-      const v2i sbm = RT ? (sb ? bm[1] : bm[0]) : bm[RT ? 0 : SB];
-      sm.bar = badd(sar.x, sar.y, sm.bar);
-      sm.bam = badd(sam.x, sam.y, sm.bam);
-      sm.bbr = badd(sbr.x, sbr.y, sm.bbr);
-      sm.bbm = badd(sbm.x, sbm.y, sm.bbm);
-      if (STAGE) stage_piece_k(stg[s], s, blk, *sr);
+      if constexpr (R::SA >= 0) {
+        sm.bar = badd(ar[R::SA].x, ar[R::SA].y, sm.bar);
+        sm.bam = badd(am[R::SA].x, am[R::SA].y, sm.bam);
+      }
+      if constexpr (R::SB >= 0) {
+        sm.bbr = badd(br[R::SB].x, br[R::SB].y, sm.bbr);
+        sm.bbm = badd(bm[R::SB].x, bm[R::SB].y, sm.bbm);
+      }
+      if (STAGE) {
+        if (R::NP == 4)
+          stage_piece_k(stg[s], s, blk, *sr);
+        else if ((s & 1) == 0)
+          stage_piece_k(stg[s >> 1], s >> 1, blk, *sr);
+      }
     }
   } else {
     // a lane's 32 operand bytes: two groups of 8 samples (rows +0..7, +8..15)
 #pragma unroll
     for (int s = 0; s < KC / 32; ++s) {
+      const bool kon = R::COMPUTE && (R::KPAR == 0 || s == R::KPAR - 1);
       v8i A[2], B[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        if (!COMPUTE && !RT && a != SA) continue;
+        if (!kon && a != R::SA) continue;
         const uint8_t* q = pa + 32 * s * PROW + 32 * a;
         const v2i w0 = lds_tr8(q), w1 = lds_tr8(q + 8 * PROW);
         const v2i r0 = hi_codes(w0), m0 = lo_codes(w0), r1 = hi_codes(w1), m1 = lo_codes(w1);
@@ -272,13 +304,13 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        if (!COMPUTE && !RT && b != SB) continue;
+        if (!kon && b != R::SB) continue;
         const uint8_t* q = pb + 32 * s * PROW + 32 * b;
         const v2i w0 = lds_tr8(q), w1 = lds_tr8(q + 8 * PROW);
         const v2i r0 = hi_codes(w0), m0 = lo_codes(w0), r1 = hi_codes(w1), m1 = lo_codes(w1);
         B[b] = v8i{r0.x, r0.y, m0.x, m0.y, r1.x, r1.y, m1.x, m1.y};
       }
-      if (COMPUTE && (!RT || mfma)) {
+      if (kon) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           // FP8 negation flips the sign bit: [r r m m] -> [-m -m r r]
@@ -287,6 +319,7 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
                             B[b][6] ^ sg, B[b][7] ^ sg, B[b][4], B[b][5]};
 #pragma unroll
           for (int a = 0; a < 2; ++a) {
+            if (R::SKIP10 && a == 1 && b == 0) continue;
             // format 0 = FP8 e4m3 for both operands; both scales 2^9
             re[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                 A[a], B[b], re[a][b], 0, 0, 0, F8_SCALE, 0, F8_SCALE);
@@ -295,15 +328,23 @@ __device__ __forceinline__ void compute_chunk(const uint8_t* __restrict__ lds, i
           }
         }
       }
-      const v8i sA = RT ? (sa ? A[1] : A[0]) : A[RT ? 0 : SA];
-      const v8i sB = RT ? (sb ? B[1] : B[0]) : B[RT ? 0 : SB];
-      sm.bar = badd(sA[4], sA[5], badd(sA[0], sA[1], sm.bar));
-      sm.bam = badd(sA[6], sA[7], badd(sA[2], sA[3], sm.bam));
-      sm.bbr = badd(sB[4], sB[5], badd(sB[0], sB[1], sm.bbr));
-      sm.bbm = badd(sB[6], sB[7], badd(sB[2], sB[3], sm.bbm));
+      if constexpr (R::SA >= 0) {
+        const v8i sA = A[R::SA];
+        sm.bar = badd(sA[4], sA[5], badd(sA[0], sA[1], sm.bar));
+        sm.bam = badd(sA[6], sA[7], badd(sA[2], sA[3], sm.bam));
+      }
+      if constexpr (R::SB >= 0) {
+        const v8i sB = B[R::SB];
+        sm.bbr = badd(sB[4], sB[5], badd(sB[0], sB[1], sm.bbr));
+        sm.bbm = badd(sB[6], sB[7], badd(sB[2], sB[3], sm.bbm));
+      }
       if (STAGE) {
-        stage_piece_k(stg[2 * s], 2 * s, blk, *sr);
-        stage_piece_k(stg[2 * s + 1], 2 * s + 1, blk, *sr);
+        if (R::NP == 4) {
+          stage_piece_k(stg[2 * s], 2 * s, blk, *sr);
+          stage_piece_k(stg[2 * s + 1], 2 * s + 1, blk, *sr);
+        } else {
+          stage_piece_k(stg[s], s, blk, *sr);
+        }
       }
     }
   }
@@ -319,6 +360,13 @@ __device__ __forceinline__ int lane_read_offset(int lane) {
   const int row = (FORM == FORM_I8 ? 8 : 16) * (g >> 1) + (j >> 1);
   return row * PROW + 16 * (g & 1) + 8 * (j & 1);
 }
+
+// Accumulator values as 32-bit words and back (by value: an element of a
+// vector register is not an object whose bytes can be reinterpreted).
+__device__ __forceinline__ uint32_t acc_bits(int x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t acc_bits(float x) { return __float_as_uint(x); }
+__device__ __forceinline__ int acc_from_bits(uint32_t b, int) { return (int)b; }
+__device__ __forceinline__ float acc_from_bits(uint32_t b, float) { return __uint_as_float(b); }
 
 __device__ __forceinline__ int to_i32(int x) { return x; }
 __device__ __forceinline__ int to_i32(float x) { return (int)x; }  // exact: integral, |x| < 2^24
@@ -416,15 +464,15 @@ struct TileCtx {
 // compute the chunk staged at `cur` while staging `stg` into `nxt`, then
 // synchronise.  Straight-line code, so that the compiler can interleave the
 // staging arithmetic with the matrix instructions.
-template <int FORM, bool COMPUTE, int SA, int SB>
+template <int FORM, class R>
 __device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, const v4i (&stg)[4],
                                             v4i (&ld)[4], int ld_chunk) {
-  load_pieces_fast(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride, x.offI,
-                   x.offJ, x.shiftI, x.shiftJ);
+  load_pieces_fast<R::NP>(ld, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride,
+                          x.offI, x.offJ, x.shiftI, x.shiftJ);
   // keep the loads at the top of the step: they have a whole step to land
   __builtin_amdgcn_sched_barrier(0);
-  compute_chunk<FORM, COMPUTE, true, SA, SB>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im,
-                                             x.sm, stg, x.lds + nxt, &x.sr);
+  compute_chunk<FORM, R, true>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, x.sm, stg,
+                               x.lds + nxt, &x.sr);
   __syncthreads();
 }
 
@@ -434,58 +482,58 @@ __device__ __forceinline__ void steady_step(TileCtx<FORM>& x, int cur, int nxt, 
 // (two register sets of raw samples).  Prefetches past the last fast chunk
 // reload that chunk, and what they stage is never computed, so the loop body
 // has no branch.
-template <int FORM, bool COMPUTE, int SA, int SB>
+template <int FORM, class R>
 __device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int nfast) {
   constexpr int B0 = 0, B1 = STAGE_LDS;
   v4i rawA[4], rawB[4];
-  load_pieces_fast(rawA, x.rows, x.row_stride, x.offI, x.offJ, x.shiftI, x.shiftJ);
-  stage_pieces(rawA, x.lds + B0, x.sr);
-  load_pieces_fast(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.offI, x.offJ,
-                   x.shiftI, x.shiftJ);
+  load_pieces_fast<R::NP>(rawA, x.rows, x.row_stride, x.offI, x.offJ, x.shiftI, x.shiftJ);
+  stage_pieces<R::NP>(rawA, x.lds + B0, x.sr);
+  load_pieces_fast<R::NP>(rawA, x.rows + (long long)KC * x.row_stride, x.row_stride, x.offI,
+                          x.offJ, x.shiftI, x.shiftJ);
   __syncthreads();
   for (int c = 0; c < nsteady; c += 2) {
-    steady_step<FORM, COMPUTE, SA, SB>(x, B0, B1, rawA, rawB, min(c + 2, nfast - 1));
-    steady_step<FORM, COMPUTE, SA, SB>(x, B1, B0, rawB, rawA, min(c + 3, nfast - 1));
-    flush_sums(x.sm, x.lds);  // two chunks: 8 x 2 (int8) or 4 x 4 (FP8) words, <= 240 a byte
+    steady_step<FORM, R>(x, B0, B1, rawA, rawB, min(c + 2, nfast - 1));
+    steady_step<FORM, R>(x, B1, B0, rawB, rawA, min(c + 3, nfast - 1));
+    // two chunks: 8 x 2 (int8) or 4 x 4 (FP8) words, <= 240 a byte
+    if (R::SUMS) flush_sums(x.sm, x.lds);
   }
 }
 
 // The same with one register set: chunk c + 1 loads at the start of chunk
 // c's step and is staged after chunk c's MFMAs.  Sixteen fewer registers,
 // for the persistent kernel, whose two tile paths share one allocation.
-template <int FORM, bool COMPUTE, int SA, int SB>
+template <int FORM, class R>
 __device__ __forceinline__ void steady_step1(TileCtx<FORM>& x, int cur, int nxt, v4i (&raw)[4],
                                              int ld_chunk) {
-  load_pieces_fast(raw, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride, x.offI,
-                   x.offJ, x.shiftI, x.shiftJ);
+  load_pieces_fast<R::NP>(raw, x.rows + (long long)ld_chunk * KC * x.row_stride, x.row_stride,
+                          x.offI, x.offJ, x.shiftI, x.shiftJ);
   __builtin_amdgcn_sched_barrier(0);
-  compute_chunk<FORM, COMPUTE, false, SA, SB>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im,
-                                              x.sm);
+  compute_chunk<FORM, R, false>(x.lds + cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, x.sm);
   __builtin_amdgcn_sched_barrier(0);
-  stage_pieces(raw, x.lds + nxt, x.sr);
+  stage_pieces<R::NP>(raw, x.lds + nxt, x.sr);
   __syncthreads();
 }
 
-template <int FORM, bool COMPUTE, int SA, int SB>
+template <int FORM, class R>
 __device__ __forceinline__ void steady_chunks1(TileCtx<FORM>& x, int nsteady, int nfast) {
   constexpr int B0 = 0, B1 = STAGE_LDS;
   v4i raw[4];
-  load_pieces_fast(raw, x.rows, x.row_stride, x.offI, x.offJ, x.shiftI, x.shiftJ);
-  stage_pieces(raw, x.lds + B0, x.sr);
+  load_pieces_fast<R::NP>(raw, x.rows, x.row_stride, x.offI, x.offJ, x.shiftI, x.shiftJ);
+  stage_pieces<R::NP>(raw, x.lds + B0, x.sr);
   __syncthreads();
   for (int c = 0; c < nsteady; c += 2) {
-    steady_step1<FORM, COMPUTE, SA, SB>(x, B0, B1, raw, min(c + 1, nfast - 1));
-    steady_step1<FORM, COMPUTE, SA, SB>(x, B1, B0, raw, min(c + 2, nfast - 1));
-    flush_sums(x.sm, x.lds);
+    steady_step1<FORM, R>(x, B0, B1, raw, min(c + 1, nfast - 1));
+    steady_step1<FORM, R>(x, B1, B0, raw, min(c + 2, nfast - 1));
+    if (R::SUMS) flush_sums(x.sm, x.lds);
   }
 }
 
-template <int FORM, bool DEEP, bool COMPUTE, int SA, int SB>
+template <int FORM, bool DEEP, class R>
 __device__ __forceinline__ void steady(TileCtx<FORM>& x, int nsteady, int nfast) {
   if (DEEP)
-    steady_chunks<FORM, COMPUTE, SA, SB>(x, nsteady, nfast);
+    steady_chunks<FORM, R>(x, nsteady, nfast);
   else
-    steady_chunks1<FORM, COMPUTE, SA, SB>(x, nsteady, nfast);
+    steady_chunks1<FORM, R>(x, nsteady, nfast);
 }
 
 // Time ranges a tile integrates: one range [t0, t1) ...
@@ -510,8 +558,8 @@ struct RunList {
 // The chunks of one time range [t_begin, t_end) of a tile, added into the
 // tile's accumulators and sums.  Returns the samples it integrated, padding
 // of a ragged last chunk included (padded samples are the code 8 + 8i).
-// COMPUTE, SA, SB: as in compute_chunk (fixed per wave, see tile_body).
-template <int FORM, bool ALIGNED, bool DEEP, bool COMPUTE, int SA, int SB>
+// R: the wave's role (see Role; fixed per wave, see tile_body).
+template <int FORM, bool ALIGNED, bool DEEP, class R>
 __device__ __forceinline__ int tile_range(TileCtx<FORM>& x, const uint8_t* __restrict__ samples,
                                           int N, int f, int nI, int nJ, int t_begin, int t_end,
                                           uint8_t* lds) {
@@ -527,7 +575,7 @@ __device__ __forceinline__ int tile_range(TileCtx<FORM>& x, const uint8_t* __res
   const int nsteady = nfast & ~1;
   int c = 0;
   if (nsteady >= 2) {
-    steady<FORM, DEEP, COMPUTE, SA, SB>(x, nsteady, nfast);
+    steady<FORM, DEEP, R>(x, nsteady, nfast);
     c = nsteady;
   }
 
@@ -536,15 +584,15 @@ __device__ __forceinline__ int tile_range(TileCtx<FORM>& x, const uint8_t* __res
   v4i raw[4];
   auto load = [&](int cc) {
     if (ALIGNED && (cc + 1) * KC <= len)
-      load_pieces_fast(raw, rows + (long long)cc * KC * row_stride, row_stride, x.offI, x.offJ,
-                       x.shiftI, x.shiftJ);
+      load_pieces_fast<R::NP>(raw, rows + (long long)cc * KC * row_stride, row_stride, x.offI,
+                              x.offJ, x.shiftI, x.shiftJ);
     else
-      load_pieces_edge(raw, samples, row_stride, f, N, nI, nJ, x.sr, t_begin + cc * KC, t_end,
-                       x.dI, x.dJ);
+      load_pieces_edge<R::NP>(raw, samples, row_stride, f, N, nI, nJ, x.sr, t_begin + cc * KC,
+                              t_end, x.dI, x.dJ);
   };
   if (c < nchunks) {
     load(c);
-    stage_pieces(raw, lds + (c & 1) * STAGE_LDS, x.sr);
+    stage_pieces<R::NP>(raw, lds + (c & 1) * STAGE_LDS, x.sr);
     __syncthreads();
   }
   for (; c < nchunks; ++c) {
@@ -552,30 +600,40 @@ __device__ __forceinline__ int tile_range(TileCtx<FORM>& x, const uint8_t* __res
     uint8_t* nxt = lds + ((c + 1) & 1) * STAGE_LDS;
     const bool more = c + 1 < nchunks;
     if (more) load(c + 1);
-    compute_chunk<FORM, COMPUTE, false, SA, SB>(cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, x.sm);
-    flush_sums(x.sm, lds);
-    if (more) stage_pieces(raw, nxt, x.sr);
+    compute_chunk<FORM, R, false>(cur, x.lane_rd, x.rowA, x.rowB, x.re, x.im, x.sm);
+    if (R::SUMS) flush_sums(x.sm, lds);
+    if (more) stage_pieces<R::NP>(raw, nxt, x.sr);
     __syncthreads();
   }
   return nchunks * KC;
 }
 
 // All ranges of a tile for one wave role.
-template <int FORM, bool ALIGNED, bool DEEP, bool COMPUTE, int SA, int SB, class Ranges>
+template <int FORM, bool ALIGNED, bool DEEP, class R, class Ranges>
 __device__ __forceinline__ int tile_ranges(TileCtx<FORM>& x, const uint8_t* __restrict__ samples,
                                            int N, int f, int nI, int nJ, const Ranges& rg,
                                            uint8_t* lds) {
   if constexpr (Ranges::kSingle) {
-    return tile_range<FORM, ALIGNED, DEEP, COMPUTE, SA, SB>(x, samples, N, f, nI, nJ,
-                                                            rg.begin(0), rg.end(0), lds);
+    return tile_range<FORM, ALIGNED, DEEP, R>(x, samples, N, f, nI, nJ, rg.begin(0), rg.end(0),
+                                              lds);
   } else {
     int teff = 0;
     for (int r = 0; r < rg.count(); ++r)
-      teff += tile_range<FORM, ALIGNED, DEEP, COMPUTE, SA, SB>(x, samples, N, f, nI, nJ,
-                                                               rg.begin(r), rg.end(r), lds);
+      teff += tile_range<FORM, ALIGNED, DEEP, R>(x, samples, N, f, nI, nJ, rg.begin(r),
+                                                 rg.end(r), lds);
     return teff;
   }
 }
+
+// LDS of a tile's epilogue, once its chunks are done: the per-input partial
+// sums (part[half][side][plane][128]) and the offset corrections (corr: 128
+// row terms, then 128 column terms) at the end of the LDS, clear of the
+// first 32 KiB, through which the two waves that share a sub-tile of a
+// diagonal tile exchange accumulators.
+constexpr int EPI_PART = LDS_BYTES - 2 * 2 * 2 * BT * 4 - 2 * BT * 8;
+constexpr int EPI_CORR = LDS_BYTES - 2 * BT * 8;
+constexpr int EPI_SWAP = 64 * 64 * 4;  // bytes one wave hands over: 64 values a lane
+static_assert(2 * EPI_SWAP <= EPI_PART, "epilogue regions overlap");
 
 // The work of one tile: baselines [I*128, I*128+128) x [J*128, J*128+128) of
 // channel f, integrated over the time ranges `rg`.  All 256 threads call it;
@@ -588,9 +646,22 @@ __device__ __forceinline__ int tile_ranges(TileCtx<FORM>& x, const uint8_t* __re
 // ALIGNED: N % 16 == 0 and the sample rows are 16-byte aligned, so that whole
 // chunks can take the fast loads.  DEEP: prefetch two chunks ahead (else one).
 //
-// Wave (wr, wc) sums A fragment wc and B fragment wr (see TileSums).  The
-// fragment choice is a compile-time parameter of the chunk loops, dispatched
-// once per tile on the wave index, so that the loops stay straight-line code.
+// Wave roles.  Off the diagonal (I < J), wave (wr, wc) computes the 64 x 64
+// sub-tile (wr, wc) and sums A fragment wc and B fragment wr, so that the
+// four waves cover the tile's 128 rows and 128 columns once.  On the diagonal
+// (I == J) sub-tile (1, 0) lies below the diagonal.  Without SPLITDIAG the
+// waves keep their roles there, and wave 2 only sums its fragments.  With
+// SPLITDIAG (fewer MFMAs and half the staging in a diagonal tile, for frames
+// with a large share of diagonal tiles), waves 0 and 3 compute the
+// diagonal sub-tiles (0, 0) and (1, 1), skipping their block below the
+// diagonal, and sum the 64 inputs of their sub-tile (rows and columns are the
+// same inputs); waves 1 and 2 share sub-tile (0, 1), wave 1 taking the even
+// and wave 2 the odd k-steps, and at the end each hands the other the half of
+// the sub-tile it does not write.  Only the I block is staged there.  A wave
+// whose blocks all lie past N computes anyway (its results are never
+// written), so that every role has one instantiation.  The role is a
+// compile-time parameter of the chunk loops, dispatched once per tile on the
+// wave index.
 //
 // Time shifting (Sec. IV-C, "Time Shifting"): with seg_delay (delays per
 // 16-input segment, in samples) and blk_delay (their maximum per 128-input
@@ -598,7 +669,7 @@ __device__ __forceinline__ int tile_ranges(TileCtx<FORM>& x, const uint8_t* __re
 // from the history the caller keeps in front of `samples`.  A block's largest
 // delay moves its (scalar) load base back; a lane's offset adds back the rows
 // its own segment is delayed less.  NULL tables: no shift.
-template <int FORM, bool ALIGNED, bool DEEP, bool SHIFT, class Ranges>
+template <int FORM, bool ALIGNED, bool DEEP, bool SHIFT, class Ranges, bool SPLITDIAG = true>
 __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, int32_t* vis,
                                           int N, long long row_stride, long long NB, int f,
                                           int I, int J, const Ranges& rg, int mode,
@@ -608,11 +679,12 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   // every branch on it is a uniform one
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = wave >> 1, wc = wave & 1;
+  const bool diag = SPLITDIAG && I == J;  // the split roles of a diagonal tile
+  const bool shared = diag && (wave == 1 || wave == 2);  // the shared sub-tile (0, 1)
+  const int wr = shared ? 0 : wave >> 1, wc = shared ? 1 : wave & 1;
 
-  // MFMA blocks of this wave that hold baselines of the triangle; a wave with
-  // none (below the diagonal, or past N) skips the MFMAs, the others compute
-  // all four blocks and drop the surplus at the write.
+  // MFMA blocks of this wave's sub-tile that hold baselines of the triangle
+  // (and, for the shared sub-tile, the half this wave writes)
   const int rs0 = I * BT + 64 * wr, cs0 = J * BT + 64 * wc;
   int mask = 0;
 #pragma unroll
@@ -620,9 +692,10 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     const int rs = rs0 + 32 * (ab >> 1), cs = cs0 + 32 * (ab & 1);
     if (rs < N && cs < N && cs >= rs) mask |= 1 << ab;
   }
+  if (shared) mask &= wave == 1 ? 0x3 : 0xC;
 
-  // staging role: every thread stages two I pieces and two J pieces (a
-  // diagonal tile stages the same rows into both blocks: no branch)
+  // staging role: every thread stages two I pieces and, off the diagonal,
+  // two J pieces
   TileCtx<FORM> x(tid);
   const int nI = I * BT + 16 * x.sr.seg, nJ = J * BT + 16 * x.sr.seg;
   // the lane's load offsets; fast loads of inputs past N (edge tiles,
@@ -662,51 +735,110 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   // the wave's role per tile (a dispatch inside a loop over ranges, or a loop
   // around one, costs the compiler many registers)
   int teff;
-#define XENG_RANGES(C, A, B) \
-  tile_ranges<FORM, ALIGNED, DEEP, C, A, B>(x, samples, N, f, nI, nJ, rg, lds)
-  if (mask) {
+#define XENG_RANGES(...) \
+  tile_ranges<FORM, ALIGNED, DEEP, Role<__VA_ARGS__>>(x, samples, N, f, nI, nJ, rg, lds)
+  if (diag) {
     switch (wave) {
-      case 0: teff = XENG_RANGES(true, 0, 0); break;
-      case 1: teff = XENG_RANGES(true, 1, 0); break;
-      case 2: teff = XENG_RANGES(true, 0, 1); break;
-      default: teff = XENG_RANGES(true, 1, 1); break;
+      case 1: teff = XENG_RANGES(-1, -1, 1, false, true); break;
+      case 2: teff = XENG_RANGES(-1, -1, 2, false, true); break;
+      default: teff = XENG_RANGES(0, 1, 0, true, true); break;
     }
   } else {
     switch (wave) {
-      case 0: teff = XENG_RANGES(false, 0, 0); break;
-      case 1: teff = XENG_RANGES(false, 1, 0); break;
-      case 2: teff = XENG_RANGES(false, 0, 1); break;
-      default: teff = XENG_RANGES(false, 1, 1); break;
+      case 0: teff = XENG_RANGES(0, 0, 0, false, false); break;
+      case 1: teff = XENG_RANGES(1, 0, 0, false, false); break;
+      case 2:
+        if (!SPLITDIAG && I == J)  // below the diagonal: sums only
+          teff = XENG_RANGES(0, 1, 0, false, false, false);
+        else
+          teff = XENG_RANGES(0, 1, 0, false, false);
+        break;
+      default: teff = XENG_RANGES(1, 1, 0, false, false); break;
     }
   }
 #undef XENG_RANGES
 
-  // Per-input sums -> offset corrections, exchanged through the second
-  // stage's LDS (free now; the sums slots lie in the first stage):
-  // part[half][side][plane][128] holds each lane's partial sums, corr the row
-  // (side 0) and column (side 1) corrections.
+  // Per-input sums -> offset corrections (see EPI_PART).  Off the diagonal a
+  // lane of wave (wr, wc) holds rows 64 wr + 32 wc + l and columns
+  // 64 wc + 32 wr + l; on the diagonal, waves 0 and 3 hold inputs 64 wr + l
+  // (A fragment 0) and 64 wr + 32 + l (B fragment 1), and the column sums
+  // are the row sums.
   if (!Ranges::kSingle && rg.count() == 0)
     __syncthreads();  // every sums slot is cleared before it is read
-  int* part = reinterpret_cast<int*>(lds + STAGE_LDS);
-  int2* corr = reinterpret_cast<int2*>(lds + STAGE_LDS + 2 * 2 * 2 * BT * 4);
+  int* part = reinterpret_cast<int*>(lds + EPI_PART);
+  int2* corr = reinterpret_cast<int2*>(lds + EPI_CORR);
   {
     const v4i sums = *reinterpret_cast<const v4i*>(sum_slot(lds));
     const int h = lane >> 5, l = lane & 31;
-    const int ra = 64 * wr + 32 * wc + l, cb = 64 * wc + 32 * wr + l;
-    part[((h * 2 + 0) * 2 + 0) * BT + ra] = sums.x;
-    part[((h * 2 + 0) * 2 + 1) * BT + ra] = sums.y;
-    part[((h * 2 + 1) * 2 + 0) * BT + cb] = sums.z;
-    part[((h * 2 + 1) * 2 + 1) * BT + cb] = sums.w;
+    if (!diag) {
+      const int ra = 64 * wr + 32 * wc + l, cb = 64 * wc + 32 * wr + l;
+      part[((h * 2 + 0) * 2 + 0) * BT + ra] = sums.x;
+      part[((h * 2 + 0) * 2 + 1) * BT + ra] = sums.y;
+      part[((h * 2 + 1) * 2 + 0) * BT + cb] = sums.z;
+      part[((h * 2 + 1) * 2 + 1) * BT + cb] = sums.w;
+    } else if (!shared) {
+      const int na = 64 * wr + l, nb = 64 * wr + 32 + l;
+      part[((h * 2 + 0) * 2 + 0) * BT + na] = sums.x;
+      part[((h * 2 + 0) * 2 + 1) * BT + na] = sums.y;
+      part[((h * 2 + 0) * 2 + 0) * BT + nb] = sums.z;
+      part[((h * 2 + 0) * 2 + 1) * BT + nb] = sums.w;
+    }
   }
-  __syncthreads();
+  __syncthreads();  // the partial sums are complete, and every sums slot has been read
   {
     const int side = tid >> 7, n = tid & (BT - 1);
-    const int sr = part[((0 * 2 + side) * 2 + 0) * BT + n] + part[((1 * 2 + side) * 2 + 0) * BT + n];
-    const int sm = part[((0 * 2 + side) * 2 + 1) * BT + n] + part[((1 * 2 + side) * 2 + 1) * BT + n];
+    const int ps = diag ? 0 : side;
+    const int sr = part[((0 * 2 + ps) * 2 + 0) * BT + n] + part[((1 * 2 + ps) * 2 + 0) * BT + n];
+    const int sm = part[((0 * 2 + ps) * 2 + 1) * BT + n] + part[((1 * 2 + ps) * 2 + 1) * BT + n];
     const Corr cr = side == 0 ? row_corr<FORM>(sr, sm, teff) : col_corr(sr, sm);
     corr[side * BT + n] = make_int2(cr.re, cr.im);
   }
+  // the shared sub-tile: wave 1 writes block row 0 and hands over its block
+  // row 1, wave 2 the reverse (lane-minor, so that the exchange is free of
+  // bank conflicts)
+  uint32_t* swap = reinterpret_cast<uint32_t*>(lds);
+  if (shared) {
+    uint32_t* give = swap + (wave == 1 ? 0 : EPI_SWAP / 4);
+    if (wave == 1) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          give[((0 * 2 + b) * 16 + v) * 64 + lane] = acc_bits(x.re[1][b][v]);
+          give[((1 * 2 + b) * 16 + v) * 64 + lane] = acc_bits(x.im[1][b][v]);
+        }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          give[((0 * 2 + b) * 16 + v) * 64 + lane] = acc_bits(x.re[0][b][v]);
+          give[((1 * 2 + b) * 16 + v) * 64 + lane] = acc_bits(x.im[0][b][v]);
+        }
+    }
+  }
   __syncthreads();
+  if (shared) {
+    typedef typename std::remove_reference<decltype(x.re[0][0][0])>::type E;
+    const uint32_t* take = swap + (wave == 1 ? EPI_SWAP / 4 : 0);
+    if (wave == 1) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          x.re[0][b][v] += acc_from_bits(take[((0 * 2 + b) * 16 + v) * 64 + lane], E{});
+          x.im[0][b][v] += acc_from_bits(take[((1 * 2 + b) * 16 + v) * 64 + lane], E{});
+        }
+    } else {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          x.re[1][b][v] += acc_from_bits(take[((0 * 2 + b) * 16 + v) * 64 + lane], E{});
+          x.im[1][b][v] += acc_from_bits(take[((1 * 2 + b) * 16 + v) * 64 + lane], E{});
+        }
+    }
+  }
   if (mask)
     write_blocks(vis, N, NB, f, rs0, cs0, 64 * wr, 64 * wc, corr, lane, mask, mode, x.re, x.im);
   __syncthreads();  // the corrections are read before the LDS is reused

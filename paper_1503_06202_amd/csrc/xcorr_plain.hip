@@ -5,7 +5,7 @@
 
 namespace xeng {
 
-template <int FORM, bool ALIGNED, bool SHIFT>
+template <int FORM, bool ALIGNED, bool SHIFT, bool SPLITDIAG = true>
 __global__ void __launch_bounds__(NTHREADS, 2) xcorr_tile_kernel(TileArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[LDS_BYTES];
   // Head items first (the dispatcher issues workgroups in order), then the
@@ -36,10 +36,11 @@ __global__ void __launch_bounds__(NTHREADS, 2) xcorr_tile_kernel(TileArgs a) {
   int I, J;
   tile_of(p, a.nt, I, J);
   const long long NB = (long long)a.N * (a.N + 1) / 2;
-  // (shifted frames prefetch one chunk ahead: the shift costs registers)
-  tile_body<FORM, ALIGNED, !SHIFT, SHIFT>(a.samples, a.vis, a.N, a.row_stride, NB, f, I, J,
-                                        OneRange{t_begin, t_end}, mode, lds, a.seg_delay,
-                                        a.blk_delay);
+  // int8 prefetches two chunks ahead; FP8 (wider operands, more registers)
+  // and shifted frames one
+  tile_body<FORM, ALIGNED, !SHIFT && FORM == FORM_I8, SHIFT, OneRange, SPLITDIAG>(
+      a.samples, a.vis, a.N, a.row_stride, NB, f, I, J, OneRange{t_begin, t_end}, mode, lds,
+      a.seg_delay, a.blk_delay);
 }
 
 // Fill int32 words with zero (kept out of hipMemsetAsync so that launches can
@@ -90,6 +91,14 @@ hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t s
   if (grid <= 0) return hipSuccess;
   if (grid > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 g((unsigned)grid), b(NTHREADS);
+  if (!a.split_diag && aligned && !a.seg_delay) {
+    // diagonal tiles keep the off-diagonal wave roles (see tile_body)
+    if (form == FORM_I8)
+      hipLaunchKernelGGL((xcorr_tile_kernel<FORM_I8, true, false, false>), g, b, 0, stream, a);
+    else
+      hipLaunchKernelGGL((xcorr_tile_kernel<FORM_F8, true, false, false>), g, b, 0, stream, a);
+    return hipGetLastError();
+  }
   XENG_DISPATCH3(xcorr_tile_kernel, form, aligned, a.seg_delay != nullptr, g, b, stream, a);
   return hipGetLastError();
 }

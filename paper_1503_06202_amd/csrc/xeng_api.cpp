@@ -442,6 +442,11 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
     a.tail_slices = tail_slices;
     a.tail_len = tail_len;
     a.tail_mode = xeng::WM_ATOMIC;
+    // Diagonal tiles split the sub-tile above the diagonal between two waves
+    // where they are a large share of the tiles (N <= 1024: at least 2 in 9);
+    // at N = 2048 (16 in 136) the uniform tile time of the common roles pays
+    // more (measured on the full-array frame).
+    a.split_diag = nt <= 8 ? 1 : 0;
     a.seg_delay = kshift ? p->d_seg_delay : nullptr;
     a.blk_delay = kshift ? p->d_blk_delay : nullptr;
     if (nslices > 1) {

@@ -34,6 +34,10 @@ struct TileArgs {
   // 128-input block (device), or NULL
   const int* seg_delay;
   const int* blk_delay;
+  // 1: diagonal tiles split the sub-tile above the diagonal between two
+  // waves and skip the block below it; 0: they keep the off-diagonal wave
+  // roles (fast loads without time shifting only; others always split)
+  int split_diag;
 };
 
 hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t stream);

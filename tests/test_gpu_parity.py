@@ -55,6 +55,17 @@ def test_odd_shapes(N, T, form):
     assert np.array_equal(gpu(s, form), want(s))
 
 
+@pytest.mark.parametrize("form", ["i8", "f8"])
+@pytest.mark.parametrize("N,T", [(1040, 200), (1152, 130), (1090, 64)])
+def test_large_n_diagonal_roles(N, T, form):
+    # above 1024 inputs the diagonal tiles of 16-aligned frames keep the
+    # off-diagonal wave roles (the wave below the diagonal only sums); below,
+    # and for unaligned frames, two waves share the sub-tile above the diagonal
+    s = rand_frame(N + T, T, 1, N)
+    print(f"large N={N} T={T} form={form}", flush=True)
+    assert np.array_equal(gpu(s, form), want(s))
+
+
 WIDE_SHAPES = [(16, 64), (48, 65), (144, 300), (256, 129), (272, 1000), (400, 64), (512, 257),
                (640, 130)]
 
