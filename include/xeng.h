@@ -306,9 +306,10 @@ int xeng_plan_batch(xeng_plan_t *out, const xeng_instance *descs, int count, uns
  * persistent kernel launch covers all instances.  An instance whose samples[k]
  * is NULL is skipped by this call (its vis[k] is ignored and untouched), so a
  * plan over a pool of slots serves any subset of them.  Pointers are copied to
- * the device through plan-owned pinned staging on the given stream; the call
- * waits on the host only when the pointers changed while the previous copy is
- * still pending.
+ * the device through plan-owned pinned staging on the given stream (a ring
+ * of four copies); the call waits on the host only when the pointers changed
+ * and the staging copy it reuses still holds an upload four calls old that
+ * has not run yet.
  * Errors: XENG_EINVAL (NULL plan or arrays, NULL vis[k] of an active
  * instance), XENG_EPLAN (not a batch plan), XENG_EHIP, XENG_ENOMEM.
  */

@@ -25,6 +25,7 @@ constexpr int kOccupancy = 2;  // workgroups per CU (LDS: 64 KiB each)
 // Output gating: extra work gates one launch segment can need when gates are
 // split (fewer than 2 x 64 = 128; see xeng_correlate_gated).
 constexpr int kSplitMax = 128;
+constexpr int kStageRing = 4;  // pinned staging copies of a batch plan's instance table
 
 enum PlanKind { PLAN_SINGLE = 1, PLAN_BATCH = 2 };
 
@@ -46,12 +47,15 @@ struct xeng_plan_s {
   std::vector<xeng::BatchItem> items;
   std::vector<int> inst_zero;
   bool any_zero = false;
-  xeng::BatchInst* h_insts = nullptr;  // pinned staging
+  // pinned staging of the instance table: a ring of kStageRing copies, so
+  // that a call refills one while earlier calls' uploads are still queued
+  xeng::BatchInst* h_insts = nullptr;
   xeng::BatchInst* d_insts = nullptr;
   xeng::BatchItem* d_items = nullptr;
   int* d_counter = nullptr;
-  hipEvent_t copy_done = nullptr;
-  bool copy_pending = false;
+  hipEvent_t copy_done[kStageRing] = {};
+  bool copy_pending[kStageRing] = {};
+  int stage_next = 0;
   std::vector<const void*> uploaded;  // pointers now in d_insts
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t capture_stream = nullptr;
@@ -895,7 +899,8 @@ static int batch_setup(xeng_plan_t p) {
   int rc = ensure_cu_count(p);
   if (rc != XENG_OK) return rc;
   const size_t ni = p->insts.size(), nw = p->items.size();
-  hipError_t e = hipHostMalloc((void**)&p->h_insts, ni * sizeof(xeng::BatchInst), hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&p->h_insts, kStageRing * ni * sizeof(xeng::BatchInst),
+                               hipHostMallocDefault);
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? XENG_ENOMEM : hip_fail(p, e, "hipHostMalloc");
   e = hipMalloc((void**)&p->d_insts, ni * sizeof(xeng::BatchInst));
   if (e == hipSuccess) e = hipMalloc((void**)&p->d_items, nw * sizeof(xeng::BatchItem));
@@ -903,7 +908,8 @@ static int batch_setup(xeng_plan_t p) {
   if (e != hipSuccess) return e == hipErrorOutOfMemory ? XENG_ENOMEM : hip_fail(p, e, "hipMalloc");
   e = hipMemcpy(p->d_items, p->items.data(), nw * sizeof(xeng::BatchItem), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(p, e, "work list upload");
-  e = hipEventCreateWithFlags(&p->copy_done, hipEventDisableTiming);
+  for (int r = 0; r < kStageRing && e == hipSuccess; ++r)
+    e = hipEventCreateWithFlags(&p->copy_done[r], hipEventDisableTiming);
   if (e != hipSuccess) return hip_fail(p, e, "hipEventCreate");
   return XENG_OK;
 }
@@ -918,16 +924,19 @@ static int batch_upload(xeng_plan_t p, const uint8_t* const* samples, int32_t* c
     same = p->uploaded[2 * k] == samples[k] &&
            p->uploaded[2 * k + 1] == (samples[k] ? vis[k] : nullptr);
   if (same) return XENG_OK;
-  if (p->copy_pending) {
-    // the pinned staging may still be read by the previous call's copy
-    hipError_t e = hipEventSynchronize(p->copy_done);
+  const int r = p->stage_next;
+  p->stage_next = (r + 1) % kStageRing;
+  if (p->copy_pending[r]) {
+    // this staging copy may still be read by an earlier call's upload
+    hipError_t e = hipEventSynchronize(p->copy_done[r]);
     if (e != hipSuccess) return hip_fail(p, e, "hipEventSynchronize");
-    p->copy_pending = false;
+    p->copy_pending[r] = false;
   }
+  xeng::BatchInst* stage = p->h_insts + (size_t)r * ni;
   p->uploaded.assign(2 * ni, nullptr);
   for (size_t k = 0; k < ni; ++k) {
     const xeng_instance& d = p->insts[k];
-    xeng::BatchInst& b = p->h_insts[k];
+    xeng::BatchInst& b = stage[k];
     b.samples = samples[k];
     b.vis = samples[k] ? vis[k] : nullptr;
     b.N = d.N;
@@ -940,14 +949,14 @@ static int batch_upload(xeng_plan_t p, const uint8_t* const* samples, int32_t* c
     p->uploaded[2 * k] = samples[k];
     p->uploaded[2 * k + 1] = b.vis;
   }
-  hipError_t e = hipMemcpyAsync(p->d_insts, p->h_insts, ni * sizeof(xeng::BatchInst),
+  hipError_t e = hipMemcpyAsync(p->d_insts, stage, ni * sizeof(xeng::BatchInst),
                                 hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipEventRecord(p->copy_done, s);
+  if (e == hipSuccess) e = hipEventRecord(p->copy_done[r], s);
   if (e != hipSuccess) {
     p->uploaded.clear();
     return hip_fail(p, e, "instance table upload");
   }
-  p->copy_pending = true;
+  p->copy_pending[r] = true;
   return XENG_OK;
 }
 
@@ -1121,7 +1130,8 @@ int xeng_destroy(xeng_plan_t p) {
   if (!p) return XENG_OK;
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
-  if (p->copy_done) (void)hipEventDestroy(p->copy_done);
+  for (int r = 0; r < kStageRing; ++r)
+    if (p->copy_done[r]) (void)hipEventDestroy(p->copy_done[r]);
   if (p->d_insts) (void)hipFree(p->d_insts);
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_counter) (void)hipFree(p->d_counter);

@@ -9,16 +9,22 @@ every ``dump_every`` frames.
 
 Continuous batching: a frame is admitted as soon as a slot (device memory for
 one in-flight frame) is free; whenever fewer than ``max_inflight`` launches
-are on the GPU, every admitted frame not yet launched goes out in one batched
-launch, so frames that arrive while others run are picked up at the next
-launch instead of waiting for a drained queue.  Frames of one stream may share
-a launch: the batched kernels add into the shared accumulator with exact
-int32 atomics.  Latency is measured from a frame's arrival to the completion
-of the launch that carried it.
+are on the GPU, the admitted frames not yet launched (up to the launcher's
+``max_batch``) go out in one batched launch, so frames that arrive while
+others run are picked up at the next launch instead of waiting for a drained
+queue.  The GPU launcher alternates launches over two HIP streams, so that a
+launch fills the compute units the previous one leaves idle as it drains.
+Frames of one stream may share a launch, and launches on both HIP streams add
+into the same accumulator: the batched kernels add with exact int32 atomics,
+whose order does not matter.  Latency is measured from a frame's arrival to
+the completion of the launch that carried it.
 
 The loop talks to a launcher (``launch``, ``ready``, ``dump``); the GPU
-launcher below drives ``libxeng.so`` through a batched plan over the slots,
-optionally replaying a captured HIP graph.
+launcher below drives ``libxeng.so`` through batched plans, one set per HIP
+stream, optionally replaying captured HIP graphs.  An integration can be
+checkpointed (``GpuLauncher.checkpoint`` with the loop's per-stream frame
+counts) and resumed in another launcher (``restore``, ``RequestLoop.run(...,
+since_dump=...)``) with the same result as an uninterrupted run.
 """
 from __future__ import annotations
 
@@ -82,18 +88,23 @@ def poisson_arrivals(n: int, rate_hz: float, seed: int) -> np.ndarray:
 class RequestLoop:
     """Admission, continuous batching, completion and dumps over a launcher."""
 
-    def __init__(self, launcher, max_inflight: int = 2, dump_every: int = 256,
+    def __init__(self, launcher, max_inflight: Optional[int] = None, dump_every: int = 256,
                  clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep):
+        if max_inflight is None:
+            max_inflight = getattr(launcher, "queues", 2)
         if launcher.slots < 1 or max_inflight < 1 or dump_every < 1:
             raise ValueError("slots, max_inflight and dump_every must be >= 1")
         self.launcher = launcher
         self.max_inflight = max_inflight
+        self.max_batch = getattr(launcher, "max_batch", launcher.slots)
         self.dump_every = dump_every
         self.clock = clock
         self.sleep = sleep
 
-    def run(self, frames: Sequence[Frame]) -> Report:
+    def run(self, frames: Sequence[Frame], since_dump: Optional[Dict[int, int]] = None) -> Report:
+        """Serve ``frames``; ``since_dump`` resumes an integration (frames already
+        integrated per stream since the last dump, e.g. from a checkpoint)."""
         frames = sorted(frames, key=lambda f: f.arrival)
         slots = self.launcher.slots
         t0 = self.clock()
@@ -101,9 +112,9 @@ class RequestLoop:
         arriving: Deque[Frame] = collections.deque(frames)
         waiting: Deque[Frame] = collections.deque()     # arrived, no slot yet
         admitted: Deque[Frame] = collections.deque()    # holds a slot, not launched
-        inflight: Deque[tuple] = collections.deque()    # (token, frames)
+        inflight: List[tuple] = []                      # (token, frames), launch order
         used = 0
-        since_dump: Dict[int, int] = collections.defaultdict(int)
+        counts: Dict[int, int] = collections.defaultdict(int, since_dump or {})
         dumps: List[Any] = []
         batch_sizes: List[int] = []
         finished: List[Frame] = []
@@ -111,22 +122,27 @@ class RequestLoop:
             t = now()
             while arriving and arriving[0].arrival <= t:
                 waiting.append(arriving.popleft())
-            # completions free their slots
-            while inflight and self.launcher.ready(inflight[0][0]):
-                _, fs = inflight.popleft()
-                td = now()
-                for f in fs:
-                    f.done = td
-                finished.extend(fs)
-                used -= len(fs)
+            # completions free their slots (launches on different HIP streams
+            # may complete out of order)
+            if inflight:
+                still = []
+                for token, fs in inflight:
+                    if self.launcher.ready(token):
+                        td = now()
+                        for f in fs:
+                            f.done = td
+                        finished.extend(fs)
+                        used -= len(fs)
+                    else:
+                        still.append((token, fs))
+                inflight = still
             while waiting and used < slots:
                 f = waiting.popleft()
                 f.admitted = t
                 admitted.append(f)
                 used += 1
             if admitted and len(inflight) < self.max_inflight:
-                batch = list(admitted)
-                admitted.clear()
+                batch = [admitted.popleft() for _ in range(min(len(admitted), self.max_batch))]
                 tl = now()
                 for f in batch:
                     f.launched = tl
@@ -135,13 +151,14 @@ class RequestLoop:
                 inflight.append((token, batch))
                 batch_sizes.append(len(batch))
                 for f in batch:
-                    since_dump[f.stream] += 1
-                # a dump is ordered after this launch, so it holds every frame of
-                # the stream launched since the previous dump (its count is kept)
+                    counts[f.stream] += 1
+                # a dump is ordered after every launch so far, so it holds every
+                # frame of the stream launched since the previous dump (its
+                # count is kept)
                 for st in sorted({f.stream for f in batch}):
-                    if since_dump[st] >= self.dump_every:
-                        dumps.append((st, since_dump[st], self.launcher.dump(st)))
-                        since_dump[st] = 0
+                    if counts[st] >= self.dump_every:
+                        dumps.append((st, counts[st], self.launcher.dump(st)))
+                        counts[st] = 0
                 continue
             if not (waiting and used < slots) and not admitted:
                 # idle until the next arrival or completion
@@ -154,55 +171,107 @@ class RequestLoop:
         wall = now()
         lat = np.array([f.latency * 1e3 for f in finished])
         rep = Report(len(finished), wall, lat, batch_sizes, dumps)
-        rep.pending = dict(since_dump)  # frames integrated since the last dump, per stream
+        rep.pending = dict(counts)  # frames integrated since the last dump, per stream
         return rep
+
+
+def slots_from_memory(frame_bytes: int, fraction: float = 0.5, cap: int = 128,
+                      device=None) -> int:
+    """Slots (frames admitted at once) that ``fraction`` of the free device
+    memory holds, at most ``cap``."""
+    import torch
+
+    free, _ = torch.cuda.mem_get_info(device)
+    return int(max(1, min(cap, (free * fraction) // max(1, frame_bytes))))
 
 
 class GpuLauncher:
     """Runs batches of frames of one shape through ``libxeng.so``.
 
-    There is one batched plan per batch size k = 1..``slots`` (k identical
-    instances (N, F, T)); a launch of k frames uses the plan of size k, whose
-    automatic time slices are chosen for k frames' worth of tiles, so that a
-    lone frame spreads over the whole GPU as well as a full batch does.
-    Every stream's accumulator lives on the GPU; frames add into it (shared,
-    atomic) and ``dump`` enqueues an asynchronous copy to pinned host memory
-    followed by a clear, all ordered on the launch stream.
+    Launches go to an idle one of ``queues`` HIP streams (default priority),
+    else to the next in turn, so that a launch starts filling the compute
+    units while the previous one drains and never queues behind a long launch
+    while another HIP stream is free.
+    Each HIP stream has its own batched plans, one per batch size k =
+    1..``max_batch`` (k identical instances (N, F, T)), because a plan takes
+    one call at a time; a plan's automatic time slices are chosen for k
+    frames' worth of tiles, so that a lone frame spreads over the whole GPU
+    as well as a full batch does.  Every stream's accumulator lives on the
+    GPU; frames add into it (shared, atomic) from either HIP stream.  ``dump``
+    is ordered after the last launch on every HIP stream, copies the
+    accumulator into one of ``dump_buffers`` pinned host buffers allocated up
+    front (in turn: a dump's buffer is reused ``dump_buffers`` dumps later),
+    and clears it; the next launches wait for the clear.
+    ``slots`` bounds the frames admitted at once (default: what half of the
+    free device memory holds, at most 128).
     """
 
-    def __init__(self, N: int, F: int, T: int, slots: int, streams: int = 1, form: str = "i8",
-                 graph: bool = True, device=None):
+    def __init__(self, N: int, F: int, T: int, slots: Optional[int] = None, streams: int = 1,
+                 form: str = "i8", graph: bool = True, device=None, max_batch: int = 8,
+                 queues: int = 2, dump_buffers: int = 4):
         import torch
 
         from .engine import BatchPlan, vis_shape
 
         self.torch = torch
         self.N, self.F, self.T = N, F, T
-        self.slots = slots
-        self.graph = graph
         self.device = device or torch.device("cuda", torch.cuda.current_device())
-        self.stream = torch.cuda.current_stream(self.device)
-        self.plans = {k: BatchPlan([(N, F, T)] * k, form=form, accumulate=True, shared_vis=True)
-                      for k in range(1, slots + 1)}
-        self.acc = [torch.zeros(vis_shape(N, F), dtype=torch.int32, device=self.device)
+        frame_bytes = N * F * T
+        self.slots = int(slots) if slots else slots_from_memory(frame_bytes, device=self.device)
+        self.max_batch = max(1, min(max_batch, self.slots))
+        self.graph = graph
+        self.queues = max(1, int(queues))
+        self.hip_streams = [torch.cuda.Stream(self.device) for _ in range(self.queues)]
+        self.plans = [{k: BatchPlan([(N, F, T)] * k, form=form, accumulate=True, shared_vis=True)
+                       for k in range(1, self.max_batch + 1)} for _ in range(self.queues)]
+        shape = vis_shape(N, F)
+        self.acc = [torch.zeros(shape, dtype=torch.int32, device=self.device)
                     for _ in range(streams)]
+        self.dump_bufs = [torch.empty(shape, dtype=torch.int32, pin_memory=True)
+                          for _ in range(max(1, dump_buffers))]
+        self.dump_events = [None] * len(self.dump_bufs)
+        self._next_dump = 0
+        self._next_q = 0
+        self._last = [None] * self.queues   # last launch event per HIP stream
+        self._cleared = None                # event after the latest accumulator clear
+        # the accumulators were written on the current stream
+        for s in self.hip_streams:
+            s.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _pick_queue(self) -> int:
+        """An idle HIP stream (its last launch has completed), else the next in turn."""
+        for i in range(self.queues):
+            q = (self._next_q + i) % self.queues
+            if self._last[q] is None or self._last[q].query():
+                return q
+        return self._next_q
 
     def launch(self, frames: List[Frame]):
+        q = self._pick_queue()
+        self._next_q = (q + 1) % self.queues
+        return self._launch_on(q, frames)
+
+    def _launch_on(self, q: int, frames: List[Frame]):
         torch = self.torch
-        plan = self.plans[len(frames)]
+        s = self.hip_streams[q]
+        if self._cleared is not None:
+            s.wait_event(self._cleared)
         samples = [f.samples for f in frames]
         vis = [self.acc[f.stream] for f in frames]
-        plan.correlate(samples, vis, stream=self.stream, graph=self.graph)
+        self.plans[q][len(frames)].correlate(samples, vis, stream=s, graph=self.graph)
         ev = torch.cuda.Event()
-        ev.record(self.stream)
+        ev.record(s)
+        self._last[q] = ev
         return ev
 
     def warm(self, samples) -> None:
         """Run every plan once (capturing its graph) on ``samples``, then clear
         the accumulators, so that no launch in a timed run pays for a capture."""
-        for k in range(1, self.slots + 1):
-            frames = [Frame(-1, 0, samples[i % len(samples)], 0.0) for i in range(k)]
-            self.launch(frames)
+        for q in range(self.queues):
+            for k in range(1, self.max_batch + 1):
+                frames = [Frame(-1, 0, samples[i % len(samples)], 0.0) for i in range(k)]
+                self._launch_on(q, frames)
+        self.torch.cuda.synchronize(self.device)
         for a in self.acc:
             a.zero_()
         self.torch.cuda.synchronize(self.device)
@@ -213,15 +282,52 @@ class GpuLauncher:
     def poll_wait(self, token) -> None:
         """Called while idle with work in flight: spin (completions take well under 1 ms)."""
 
+    def _after_all(self):
+        """A HIP stream ordered after the last launch on every HIP stream."""
+        s = self.hip_streams[0]
+        for q in range(1, self.queues):
+            if self._last[q] is not None:
+                s.wait_event(self._last[q])
+        return s
+
     def dump(self, stream: int):
         torch = self.torch
-        host = torch.empty(self.acc[stream].shape, dtype=torch.int32, pin_memory=True)
-        host.copy_(self.acc[stream], non_blocking=True)
-        self.acc[stream].zero_()
+        s = self._after_all()
+        b = self._next_dump
+        self._next_dump = (b + 1) % len(self.dump_bufs)
+        if self.dump_events[b] is not None:
+            self.dump_events[b].synchronize()  # its previous copy has landed
+        host = self.dump_bufs[b]
+        with torch.cuda.stream(s):
+            host.copy_(self.acc[stream], non_blocking=True)
+            self.acc[stream].zero_()
         ev = torch.cuda.Event()
-        ev.record(self.stream)
+        ev.record(s)
+        self.dump_events[b] = ev
+        self._cleared = ev
         return (stream, host, ev)
 
+    def checkpoint(self) -> List[Any]:
+        """Host copies of every accumulator, after all launched work (blocks)."""
+        s = self._after_all()
+        s.synchronize()
+        return [a.cpu().clone() for a in self.acc]
+
+    def restore(self, state: Sequence[Any]) -> None:
+        """Load accumulators saved by ``checkpoint`` (into this launcher)."""
+        torch = self.torch
+        if len(state) != len(self.acc):
+            raise ValueError("checkpoint holds a different number of streams")
+        s = self._after_all()
+        with torch.cuda.stream(s):
+            for a, h in zip(self.acc, state):
+                a.copy_(torch.as_tensor(h).to(self.device, non_blocking=False))
+        ev = torch.cuda.Event()
+        ev.record(s)
+        self._cleared = ev
+        s.synchronize()
+
     def close(self) -> None:
-        for p in self.plans.values():
-            p.close()
+        for q in self.plans:
+            for p in q.values():
+                p.close()
