@@ -31,6 +31,8 @@ _LIBS: dict = {}
 
 def load(mutant: Optional[str] = None, path: Optional[str] = None) -> ctypes.CDLL:
     """Load (building it first if absent) the oracle library."""
+    if not path and not mutant and os.environ.get("ORACLE_LIBRARY"):
+        path = os.environ["ORACLE_LIBRARY"]  # another build of the same source
     key = path or mutant or ""
     if key in _LIBS:
         return _LIBS[key]

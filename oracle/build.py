@@ -18,16 +18,24 @@ FLAG_MUTANTS = ("FLAG",)    # planted mistakes of the flagged mode only
 BEAM_MUTANTS = ("BEAMCONJ",)  # planted mistakes of the beamformer only
 
 
-def lib_path(mutant: str | None = None, outdir: str | None = None) -> str:
+def lib_path(mutant: str | None = None, outdir: str | None = None, sanitize: bool = False) -> str:
     name = "liboracle.so" if not mutant else f"liboracle_mutant_{mutant.lower()}.so"
+    if sanitize:
+        name = name.replace(".so", "_san.so")
     return os.path.join(outdir or HERE, name)
 
 
-def build(mutant: str | None = None, outdir: str | None = None, quiet: bool = True) -> str:
-    out = lib_path(mutant, outdir)
+def build(mutant: str | None = None, outdir: str | None = None, quiet: bool = True,
+          sanitize: bool = False) -> str:
+    """sanitize: a copy built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (load it with gcc's libasan preloaded, and ORACLE_LIBRARY naming it)."""
+    out = lib_path(mutant, outdir, sanitize)
     cc = os.environ.get("CC", "gcc")
     cmd = [cc, "-O3", "-march=native", "-fopenmp", "-fPIC", "-shared", "-std=c11",
            "-Wall", "-Wextra", "-o", out + ".tmp", SRC]
+    if sanitize:
+        cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                    "-fno-omit-frame-pointer", "-g"]
     if mutant:
         if mutant not in MUTANTS + SHIFT_MUTANTS + FLAG_MUTANTS + BEAM_MUTANTS:
             raise ValueError(f"unknown mutant {mutant}")

@@ -8,7 +8,10 @@ from __future__ import annotations
 import ctypes
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libxeng.so")
+# the in-tree library; XENG_LIBRARY names another build of the same sources
+# (the host-sanitizer build that the CPU tests load in a child process)
+LIB_PATH = os.environ.get("XENG_LIBRARY") or os.path.join(
+    os.path.dirname(os.path.abspath(__file__)), "libxeng.so")
 
 XENG_OK = 0
 XENG_EINVAL = -1

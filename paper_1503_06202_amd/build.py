@@ -67,6 +67,48 @@ def _run(cmd: list, what: str, quiet: bool) -> None:
         print(msg)
 
 
+# Host-side sanitizer build of the C ABI (argument checks, plans, work lists):
+# xeng_api.cpp is compiled with AddressSanitizer and UndefinedBehaviorSanitizer
+# for the host only and linked with the ordinary kernel objects into
+# _build/libxeng_san.so.  Load it with XENG_LIBRARY pointing at it and clang's
+# ASan runtime preloaded (asan_runtime()).
+SAN_LIB = os.path.join(OBJDIR, "libxeng_san.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host",
+             "-fno-omit-frame-pointer"]
+
+
+def asan_runtime() -> str:
+    """clang's shared AddressSanitizer runtime (to preload for libxeng_san.so)."""
+    res = subprocess.run([hipcc(), "--print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True)
+    path = res.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+        import glob
+
+        hits = glob.glob(os.path.join(rocm, "lib/llvm/lib/clang/*/lib/*/libclang_rt.asan-x86_64.so"))
+        hits += glob.glob(os.path.join(rocm, "llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+        path = hits[0] if hits else ""
+    return path
+
+
+def build_sanitized(quiet: bool = True) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    for src in SOURCES:
+        if src != "xeng_api.cpp" and not os.path.exists(object_path(src)):
+            _run(compile_command(src), src, quiet)
+    san_obj = os.path.join(OBJDIR, "xeng_api_san.o")
+    _run([hipcc()] + FLAGS + SAN_FLAGS + ["-c", os.path.join(CSRC, "xeng_api.cpp"), "-o", san_obj],
+         "xeng_api.cpp (sanitized)", quiet)
+    objs = [object_path(s) for s in SOURCES if s != "xeng_api.cpp"] + [san_obj]
+    tmp = SAN_LIB + ".tmp"
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-shared-libsan", "-Xarch_host",
+          "-fsanitize=address,undefined", "-o", tmp] + objs, "libxeng_san", quiet)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 def build(quiet: bool = True, jobs: int = 0) -> str:
     from concurrent.futures import ThreadPoolExecutor
 
