@@ -116,10 +116,16 @@ int xeng_correlate(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
  *            int32 atomic adds into vis, which are exact);
  *   kernel   tile shape: 1 = 128 x 128 baselines per workgroup (two
  *            workgroups per CU), 2 = 128 x 256 (one per CU; used only when
- *            N % 16 == 0 and the samples are 16-byte aligned, else 1).
- *            Automatic: 1, the faster of the two on gfx950 at every
- *            measured size.
- * Errors: XENG_EINVAL (NULL plan, negative split_t, kernel outside 0..2).
+ *            N % 16 == 0 and the samples are 16-byte aligned, else 1),
+ *            3 / 4 = 128 x 128 with the wave roles of diagonal tiles fixed:
+ *            3 splits the sub-tile above the diagonal between two waves and
+ *            skips the block below it, 4 keeps the off-diagonal roles (4
+ *            applies to 16-byte-aligned frames without time shifting; others
+ *            always split).  1 chooses the diagonal roles by N (split up to
+ *            1024 inputs).  Automatic: 1, the fastest of these on gfx950 at
+ *            the measured sizes; the autotuner (tune.tune_plain) picks per
+ *            shape.
+ * Errors: XENG_EINVAL (NULL plan, negative split_t, kernel outside 0..4).
  */
 int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel);
 

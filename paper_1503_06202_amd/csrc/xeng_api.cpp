@@ -38,7 +38,8 @@ struct xeng_plan_s {
   int form = XENG_FORM_I8;
   bool accumulate = false;
   int split_t = 0;  // 0 = automatic
-  int kernel = 0;   // 0 = automatic, 1 = 128 x 128 tiles, 2 = 128 x 256 tiles
+  int kernel = 0;   // 0 = automatic, 1 = 128 x 128 tiles, 2 = 128 x 256 tiles,
+                    // 3 / 4 = 128 x 128 tiles with split / common diagonal roles
   int cu_count = 0;
   std::string err;
 
@@ -356,7 +357,7 @@ int xeng_plan_set_delays(xeng_plan_t p, const int32_t* delays, int D_max) {
 }
 
 int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel) {
-  if (!p || split_t < 0 || kernel < 0 || kernel > 2) return XENG_EINVAL;
+  if (!p || split_t < 0 || kernel < 0 || kernel > 4) return XENG_EINVAL;
   p->split_t = split_t;
   p->kernel = kernel;
   return XENG_OK;
@@ -450,7 +451,7 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
     // where they are a large share of the tiles (N <= 1024: at least 2 in 9);
     // at N = 2048 (16 in 136) the uniform tile time of the common roles pays
     // more (measured on the full-array frame).
-    a.split_diag = nt <= 8 ? 1 : 0;
+    a.split_diag = p->kernel == 3 ? 1 : p->kernel == 4 ? 0 : (nt <= 8 ? 1 : 0);
     a.seg_delay = kshift ? p->d_seg_delay : nullptr;
     a.blk_delay = kshift ? p->d_blk_delay : nullptr;
     if (nslices > 1) {

@@ -1,4 +1,15 @@
-"""Autotuner of the batched form: time slices per tile for each instance shape.
+"""Autotuners: tile shape and time slices of a plain plan, and time slices
+per instance shape of a batched plan.
+
+Plain form (``tune_plain``): for one frame shape (N, F, T) the tuner times
+every tile shape the library has on seeded synthetic frames of that shape:
+128 x 128 tiles with split or common wave roles in diagonal tiles (kernel 3
+or 4 of ``xeng_plan_set_tuning``) and 128 x 256 tiles (kernel 2), each with
+the automatic time slices and with 1, 2 and 4 slices.  It rejects any
+candidate whose output is not bit-identical to the first candidate's, keeps
+the fastest, and caches it as JSON keyed by (arch, form, N, F, T).
+
+Batched form (``tune``):
 
 A batched plan launches one persistent kernel over the tiles of every
 instance.  Splitting an instance's integration into several time slices gives
@@ -47,6 +58,78 @@ def save_cache(path: str, cache: Dict[str, dict]) -> None:
     with open(tmp, "w") as fh:
         json.dump(cache, fh, indent=1, sort_keys=True)
     os.replace(tmp, path)
+
+
+PLAIN_KERNELS = (3, 4, 2)     # 128x128 split diagonal, 128x128 common, 128x256
+PLAIN_SPLITS = (0, 1, 2, 4)   # 0: automatic
+
+
+def _time_plain(shape, form: str, kernel: int, split: int, frame, reps: int):
+    import torch
+
+    from .engine import Plan
+
+    N, F, T = shape
+    with Plan(N, F, T, form=form, split_t=split, kernel=kernel) as p:
+        out = p.correlate(frame)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(reps):
+            e0.record()
+            p.correlate(frame, out)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2], out
+
+
+def tune_plain(N: int, F: int, T: int, form: str = "i8", kernels: Iterable[int] = PLAIN_KERNELS,
+               splits: Iterable[int] = PLAIN_SPLITS, reps: int = 5,
+               cache_path: Optional[str] = DEFAULT_CACHE, seed: int = 4321, frame=None,
+               log=None) -> Tuple[int, int]:
+    """(kernel, split_t) for ``Plan.set_tuning`` on frames of this shape.
+
+    ``frame`` (optional): a device frame of the shape to time on, instead of a
+    freshly generated one.
+    """
+    import torch
+
+    import synth
+
+    key = "plain/" + _key(_arch(), form, N, F, T)
+    cache = load_cache(cache_path) if cache_path else {}
+    if key in cache:
+        return int(cache[key]["kernel"]), int(cache[key]["split_t"])
+    if frame is None:
+        frame = torch.from_numpy(synth.gen_frame(N, F, T, seed, "gauss",
+                                                 stream_key=(0x7F, N, T))).cuda()
+    results, ref = {}, None
+    for kernel in kernels:
+        if kernel == 2 and N % 16:
+            continue  # 128 x 256 tiles need 16-aligned inputs
+        for split in splits:
+            if split > max(1, T // 64):
+                continue
+            ms, out = _time_plain((N, F, T), form, kernel, split, frame, reps)
+            if ref is None:
+                ref = out
+            elif not torch.equal(out, ref):  # never keep a candidate that changes a bit
+                if log:
+                    log(f"tune: {key} kernel {kernel} split {split} rejected (not bit-exact)")
+                continue
+            results[(kernel, split)] = ms
+    choice = min(results, key=results.get)
+    cache[key] = {"kernel": choice[0], "split_t": choice[1],
+                  "ms": {f"{k}/{s}": v for (k, s), v in sorted(results.items())}}
+    if log:
+        log(f"tune: {key}: " + ", ".join(f"kernel {k} split {s}: {v:.3f} ms"
+                                          for (k, s), v in sorted(results.items())) +
+            f" -> kernel {choice[0]} split {choice[1]}")
+    if cache_path:
+        save_cache(cache_path, cache)
+    return choice
 
 
 def _time_batch(shape: Tuple[int, int, int], copies: int, split: int, form: str, frames,
