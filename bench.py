@@ -27,6 +27,27 @@ METRIC = ("complex MACs/s and % int8 MFMA peak at N=2048; channels sustained rea
           "p99 frame latency")
 PEAK_TOPS = {"i8": 5000.0, "f8": 5000.0}   # dense MFMA peaks of MI355X (int8 TOP/s, FP8 TFLOP/s)
 HBM_GBPS = 8000.0                           # HBM3E bandwidth of MI355X, GB/s
+
+# The sources each measured kernel is built from: a traffic figure in
+# profiles/traffic.json counts only while their digest matches the one stored
+# with it (counters taken on another version of the kernel are reported null).
+KERNEL_SOURCES = {
+    "full_array/i8": ("xcorr_device.hpp", "xcorr_plain.hip", "xcorr_tile.hpp",
+                      "xeng_internal.hpp"),
+    "full_array/f8": ("xcorr_device.hpp", "xcorr_plain.hip", "xcorr_tile.hpp",
+                      "xeng_internal.hpp"),
+    "full_array/beams16": ("xeng_beam.hip", "xeng_internal.hpp"),
+}
+
+
+def kernel_sources_sha(key):
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES.get(key, ()):
+        with open(os.path.join(ROOT, "paper_1503_06202_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 SAMPLE_PERIOD_S = 21.47 / 2 ** 23          # one sample per channel every 2.56 us
 CHANNEL_MHZ = 400.0 / 1024                 # 1024 channels over 400 MHz
 
@@ -524,12 +545,17 @@ def main():
     channels_rt = w.F * frame_s / (ms_step / 1e3)
 
     traffic = None
+    traffic_note = "no counters for this kernel"
     if os.path.exists(args.traffic):
         with open(args.traffic) as fh:
             tr = json.load(fh)
         key = f"{w.name}/{args.form}"
         if key in tr:
-            traffic = tr[key].get("bytes_per_launch")
+            if tr[key].get("sources_sha256") == kernel_sources_sha(key):
+                traffic = tr[key].get("bytes_per_launch")
+                traffic_note = tr[key].get("source", "")
+            else:
+                traffic_note = "counters were taken on another version of the kernel"
 
     out = {
         "metric": METRIC,
@@ -553,7 +579,7 @@ def main():
         "kernel_ms_avg": ev_avg,
         "kernel_ms_min": min(ev_ms),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic},
+                     "frac": achieved / peak, "traffic": traffic, "traffic_note": traffic_note},
     }
     out["config"]["sha256"] = synth.frame_sha256(frame)
     # Host-fed rate, beside (never instead of) the device-resident value: one
