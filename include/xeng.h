@@ -91,7 +91,9 @@ int xeng_version(void);
 const char *xeng_strerror(int code);
 
 /*
- * Create a plan for frames of N inputs, F channels and at most T_max samples.
+ * Create a plan for frames of N inputs, F channels and at most T_max samples
+ * (the X-engine of Sec. IV-C, "Full Correlation": one frequency band per
+ * channel, N(N+1)/2 baselines each by Eq. (1)).
  * flags: one XENG_FORM_* value, optionally | XENG_ACCUMULATE.  The plan does
  * no HIP call; workspace, if a call needs any, is allocated on first use.
  * Errors: XENG_EINVAL (out NULL, N, F or T_max < 1, N > XENG_N_MAX, unknown flag bits),
@@ -100,7 +102,9 @@ const char *xeng_strerror(int code);
 int xeng_plan(xeng_plan_t *out, int N, int F, int T_max, unsigned flags);
 
 /*
- * Correlate one frame: vis (see layout above) from samples[T][F][N].
+ * Correlate one frame: vis (see layout above) from samples[T][F][N], the
+ * integrated pairwise products of all inputs in every band (Sec. I; Sec. IV-C,
+ * "Full Correlation"; Eq. (1)) on the offset-binary samples of Sec. II-A.
  * N and F must equal the plan's, 1 <= T <= T_max.  With XENG_ACCUMULATE in the
  * plan, the frame's sums are added to vis; otherwise vis is overwritten.
  * Errors: XENG_EINVAL (NULL plan or pointer, T < 1), XENG_EPLAN (N or F differ
@@ -297,7 +301,8 @@ typedef struct xeng_instance {
 
 /*
  * Plan a batch of `count` instances (copied; descs may be freed after the
- * call).  flags as for xeng_plan (the form applies to every instance), plus
+ * call).  Each instance is the correlation of xeng_correlate (Sec. IV-C,
+ * "Full Correlation"; Eq. (1)) on its own frame.  flags as for xeng_plan (the form applies to every instance), plus
  * XENG_SHARED_VIS, which needs XENG_ACCUMULATE.  The plan owns a device table
  * of work items, built on first use.
  * Errors: XENG_EINVAL (out or descs NULL, count < 1, any N, F or T < 1,
@@ -307,8 +312,9 @@ typedef struct xeng_instance {
 int xeng_plan_batch(xeng_plan_t *out, const xeng_instance *descs, int count, unsigned flags);
 
 /*
- * Correlate every instance of a batch plan: samples[k] and vis[k] are the
- * device buffers of instance k (host arrays of count device pointers).  One
+ * Correlate every instance of a batch plan (the definition of
+ * xeng_correlate, Sec. IV-C "Full Correlation", per instance): samples[k] and
+ * vis[k] are the device buffers of instance k (host arrays of count device pointers).  One
  * persistent kernel launch covers all instances.  An instance whose samples[k]
  * is NULL is skipped by this call (its vis[k] is ignored and untouched), so a
  * plan over a pool of slots serves any subset of them.  Pointers are copied to
