@@ -126,10 +126,15 @@ int xeng_correlate(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
  *            skips the block below it, 4 keeps the off-diagonal roles (4
  *            applies to 16-byte-aligned frames without time shifting; others
  *            always split).  1 chooses the diagonal roles by N (split up to
- *            1024 inputs).  Automatic: 1, the fastest of these on gfx950 at
- *            the measured sizes; the autotuner (tune.tune_plain) picks per
- *            shape.
- * Errors: XENG_EINVAL (NULL plan, negative split_t, kernel outside 0..4).
+ *            1024 inputs).  5 = the channel kernel: one workgroup of eight
+ *            waves per (channel, time slice) covers the whole triangle of a
+ *            channel of at most 256 inputs, each sample read once (int8 form
+ *            only; the FP8 form, time shifting through the loads and N > 256
+ *            use 1).  Automatic: 5 for the int8 form at 128 < N <= 256 with
+ *            N % 16 == 0 and 16-byte-aligned samples, else 1, the fastest on
+ *            gfx950 at the measured sizes; the autotuner (tune.tune_plain)
+ *            picks per shape.
+ * Errors: XENG_EINVAL (NULL plan, negative split_t, kernel outside 0..5).
  */
 int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel);
 

@@ -17,9 +17,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libxeng.so")
 CEILING = os.path.join(PKG, "mfma_ceiling")
-SOURCES = ("xcorr_plain.hip", "xcorr_gated.hip", "xcorr_batch.hip", "xcorr_wide.hip",
-           "xeng_flags.hip", "xeng_beam.hip", "xeng_shift.hip", "xeng_noalloc.hip",
-           "xeng_api.cpp")
+SOURCES = ("xcorr_plain.hip", "xcorr_chan.hip", "xcorr_gated.hip", "xcorr_batch.hip",
+           "xcorr_wide.hip", "xeng_flags.hip", "xeng_beam.hip", "xeng_shift.hip",
+           "xeng_noalloc.hip", "xeng_api.cpp")
 OBJDIR = os.path.join(PKG, "_build")
 ARCH = "gfx950"
 

@@ -22,6 +22,7 @@ namespace {
 constexpr int kTile = 128;   // tile edge of the kernels
 constexpr int kChunk = 64;   // samples per staged chunk
 constexpr int kOccupancy = 2;  // workgroups per CU (LDS: 64 KiB each)
+constexpr int kChanMax = 2 * kTile;  // inputs of the channel kernel
 // Output gating: extra work gates one launch segment can need when gates are
 // split (fewer than 2 x 64 = 128; see xeng_correlate_gated).
 constexpr int kSplitMax = 128;
@@ -357,7 +358,7 @@ int xeng_plan_set_delays(xeng_plan_t p, const int32_t* delays, int D_max) {
 }
 
 int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel) {
-  if (!p || split_t < 0 || kernel < 0 || kernel > 4) return XENG_EINVAL;
+  if (!p || split_t < 0 || kernel < 0 || kernel > 5) return XENG_EINVAL;
   p->split_t = split_t;
   p->kernel = kernel;
   return XENG_OK;
@@ -389,6 +390,10 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
   // wide tiles (128 x 256, one workgroup per CU) only on request and when
   // the rows allow fast loads; 128 x 128 (two workgroups per CU) otherwise
   const bool wide = aligned && p->kernel == 2 && !kshift;
+  // the channel kernel (int8, N <= 256): on request, or automatically above
+  // one tile edge when the rows allow fast loads
+  const bool chan = p->form == XENG_FORM_I8 && !kshift && N <= kChanMax &&
+                    (p->kernel == 5 || (p->kernel == 0 && N > kTile && aligned));
   const long long tpc = wide ? wide_tiles_per_channel(N) : tiles_per_channel(N);
   const int occupancy = wide ? 1 : kOccupancy;
   // The FP8 form integrates at most XENG_F8_FLUSH_MAX samples per launch (f32
@@ -399,6 +404,35 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
   const int seg = p->form == XENG_FORM_F8 ? XENG_F8_FLUSH_MAX : (wide ? T : XENG_I8_SEG_MAX);
   for (int t0 = 0; t0 < T; t0 += seg) {
     const int t1 = std::min(T, t0 + seg), len = t1 - t0;
+    if (chan) {
+      // one work item per (channel, slice), one workgroup per CU
+      int ns = p->split_t > 0 ? p->split_t : auto_slices(F, len, p->cu_count, 1);
+      ns = std::min(ns, (len + kChunk - 1) / kChunk);
+      int sl = (len + ns - 1) / ns;
+      sl = (sl + kChunk - 1) / kChunk * kChunk;
+      ns = (len + sl - 1) / sl;
+      const bool add = p->accumulate || t0 > 0;
+      xeng::ChanArgs c;
+      c.samples = samples;
+      c.vis = vis;
+      c.N = N;
+      c.F = F;
+      c.t0 = t0;
+      c.t1 = t1;
+      c.nslices = ns;
+      c.slice_len = sl;
+      c.row_stride = (long long)F * N;
+      const bool wide_atomics = (reinterpret_cast<uintptr_t>(vis) & 7) == 0;
+      c.write_mode = ns > 1 ? (wide_atomics ? xeng::WM_ATOMIC64 : xeng::WM_ATOMIC)
+                            : (add ? xeng::WM_ADD : xeng::WM_STORE);
+      if (ns > 1 && !add) {
+        hipError_t e = xeng::launch_zero(vis, (long long)F * N * (N + 1), s);
+        if (e != hipSuccess) return hip_fail(p, e, "zero fill launch");
+      }
+      hipError_t e = xeng::launch_chan(c, aligned, s);
+      if (e != hipSuccess) return hip_fail(p, e, "channel kernel launch");
+      continue;
+    }
     const long long W = tpc * F;  // tiles of the launch
     int nslices = p->split_t > 0 ? p->split_t : auto_slices(W, len, p->cu_count, occupancy);
     nslices = std::min(nslices, (len + kChunk - 1) / kChunk);

@@ -104,7 +104,9 @@ class Plan:
     def set_tuning(self, split_t: int = 0, kernel: int = 0) -> None:
         """split_t: time slices per tile (0 = automatic); kernel: 0 automatic,
         1 = 128 x 128 tiles, 2 = 128 x 256 tiles (needs N % 16 == 0), 3 / 4 =
-        128 x 128 tiles with split / common wave roles in diagonal tiles."""
+        128 x 128 tiles with split / common wave roles in diagonal tiles, 5 =
+        the channel kernel (one workgroup per channel and time slice; int8,
+        N <= 256; other plans use 1)."""
         _lib.check(_lib.lib().xeng_plan_set_tuning(self._h, int(split_t), int(kernel)),
                    "xeng_plan_set_tuning")
 

@@ -60,7 +60,7 @@ def save_cache(path: str, cache: Dict[str, dict]) -> None:
     os.replace(tmp, path)
 
 
-PLAIN_KERNELS = (3, 4, 2)     # 128x128 split diagonal, 128x128 common, 128x256
+PLAIN_KERNELS = (5, 3, 4, 2)  # channel kernel, 128x128 split diagonal, 128x128 common, 128x256
 PLAIN_SPLITS = (0, 1, 2, 4)   # 0: automatic
 
 
@@ -109,6 +109,8 @@ def tune_plain(N: int, F: int, T: int, form: str = "i8", kernels: Iterable[int] 
     for kernel in kernels:
         if kernel == 2 and N % 16:
             continue  # 128 x 256 tiles need 16-aligned inputs
+        if kernel == 5 and (N > 256 or form != "i8"):
+            continue  # the channel kernel: int8, at most 256 inputs
         for split in splits:
             if split > max(1, T // 64):
                 continue

@@ -74,9 +74,9 @@ def test_correlate_validation_needs_no_gpu(L):
         assert L.xeng_correlate(h, dummy, 64, 2, 1001, dummy, None) == _lib.XENG_EPLAN
         assert L.xeng_correlate(h, dummy, 64, 2, 1 << 24, dummy, None) == _lib.XENG_EOVERFLOW
         assert L.xeng_plan_set_tuning(h, -1, 0) == _lib.XENG_EINVAL
-        assert L.xeng_plan_set_tuning(h, 3, 5) == _lib.XENG_EINVAL
+        assert L.xeng_plan_set_tuning(h, 3, 6) == _lib.XENG_EINVAL
         assert L.xeng_plan_set_tuning(h, 3, -1) == _lib.XENG_EINVAL
-        for k in (0, 1, 2, 3, 4):
+        for k in (0, 1, 2, 3, 4, 5):
             assert L.xeng_plan_set_tuning(h, 3, k) == _lib.XENG_OK
         assert L.xeng_plan_error(h) == b""
     finally:
