@@ -25,12 +25,17 @@ __global__ void __launch_bounds__(NTHREADS, 2)
     if (!in.samples) continue;  // instance not active in this call (uniform branch)
     const long long NB = (long long)in.N * (in.N + 1) / 2;
     const long long stride = (long long)in.F * in.N;
+    // int8 prefetches two chunks ahead on the fast path (as the plain kernel
+    // does); FP8 one
+    // (64-bit atomic adds for the tiles of time-sliced instances)
     if (in.aligned)
-      tile_body<FORM, true, false, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J,
-                                   OneRange{it.t0, it.t1}, it.mode, lds);
+      tile_body<FORM, true, FORM == FORM_I8, false, OneRange, true, true>(
+          in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J, OneRange{it.t0, it.t1}, it.mode,
+          lds);
     else
-      tile_body<FORM, false, false, false>(in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J,
-                                    OneRange{it.t0, it.t1}, it.mode, lds);
+      tile_body<FORM, false, false, false, OneRange, true, true>(
+          in.samples, in.vis, in.N, stride, NB, it.f, it.I, it.J, OneRange{it.t0, it.t1}, it.mode,
+          lds);
   }
 }
 

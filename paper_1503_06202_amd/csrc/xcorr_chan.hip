@@ -141,11 +141,6 @@ struct ChanOut {
   const int2* S;  // per-input code sums (LDS)
 };
 
-// b(i, j) = i N - i (i - 1) / 2 + (j - i), the packed row-major triangle.
-__device__ __forceinline__ int32_t* at(const ChanOut& o, int i, int j) {
-  return o.base + 2 * (i * o.N - ((i * (i - 1)) >> 1) + (j - i));
-}
-
 // Row of register v in a lane's share of a 32 x 32 MFMA block (its column is
 // lane % 32).
 __device__ __forceinline__ int blk_row(int v, int lane) {
@@ -153,53 +148,20 @@ __device__ __forceinline__ int blk_row(int v, int lane) {
 }
 
 // A lane's share of a block, (vr, vi) of baselines (i0 + blk_row(v), j) for
-// the v set in `ok`, into vis in write mode MODE.
-//
-// WM_ATOMIC64: the pair (re, im), read as the 64-bit integer
-// re + 2^32 (im + [re < 0]), takes one atomic add of vr + 2^32 vi, which is
-// exact; the add moves a borrow between the words exactly when the sign of
-// the real word changes (the returned old value tells), and a 32-bit add on
-// the imaginary word takes it back.  Once every add of a launch has landed
-// the pair is (sum re, sum im) again, so time slices that add into one
-// baseline cost one wide atomic each instead of two.  All sixteen wide adds
-// issue before the first returned value is needed.
+// the v set in `ok`, into vis in write mode MODE (see put_pairs).
 template <int MODE>
 __device__ __forceinline__ void store16(const ChanOut& o, int i0, int j, int lane,
                                         const int (&vr)[16], const int (&vi)[16], uint32_t ok) {
-  if constexpr (MODE == WM_ATOMIC64) {
-    uint32_t old[16];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      old[v] = 0u;
-      if (ok & (1u << v)) {
-        const unsigned long long add =
-            ((unsigned long long)(uint32_t)vi[v] << 32) + (unsigned long long)(long long)vr[v];
-        old[v] = (uint32_t)atomicAdd(
-            reinterpret_cast<unsigned long long*>(at(o, i0 + blk_row(v, lane), j)), add);
-      }
-    }
+  for (int h = 0; h < 2; ++h) {
+    int b[8], r[8], m[8];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int re0 = (int)old[v];
-      const int re1 = (int)(old[v] + (uint32_t)vr[v]);
-      const int fix = (re1 < 0) - (re0 < 0);
-      if ((ok & (1u << v)) && fix) atomicAdd(at(o, i0 + blk_row(v, lane), j) + 1, fix);
+    for (int u = 0; u < 8; ++u) {
+      b[u] = pair_index(i0 + blk_row(8 * h + u, lane), j, o.N);
+      r[u] = vr[8 * h + u];
+      m[u] = vi[8 * h + u];
     }
-  } else {
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      if (!(ok & (1u << v))) continue;
-      int32_t* p = at(o, i0 + blk_row(v, lane), j);
-      if constexpr (MODE == WM_STORE) {
-        *reinterpret_cast<int2*>(p) = make_int2(vr[v], vi[v]);
-      } else if constexpr (MODE == WM_ADD) {
-        const int2 q = *reinterpret_cast<int2*>(p);
-        *reinterpret_cast<int2*>(p) = make_int2(q.x + vr[v], q.y + vi[v]);
-      } else {
-        atomicAdd(p, vr[v]);
-        if (vi[v]) atomicAdd(p + 1, vi[v]);
-      }
-    }
+    put_pairs<MODE>(o.base, b, r, m, (ok >> (8 * h)) & 0xFFu);
   }
 }
 
@@ -534,7 +496,7 @@ __device__ __forceinline__ void chan_wave(const ChanArgs& a, int f, int t_begin,
   // waves 6 and 7 transpose their diagonal blocks through the (free) stages
   int* m = reinterpret_cast<int*>(lds) + (wave & 1) * 4 * (CH_DIAG / 4);
   // one dispatch on the (uniform) write mode
-  switch (a.write_mode) {
+  switch (wide_atomics(a.write_mode, a.vis)) {
     case WM_STORE: role.template write<WM_STORE>(o, m, lane); break;
     case WM_ADD: role.template write<WM_ADD>(o, m, lane); break;
     case WM_ATOMIC64: role.template write<WM_ATOMIC64>(o, m, lane); break;

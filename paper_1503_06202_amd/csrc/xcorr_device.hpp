@@ -391,15 +391,123 @@ __device__ __forceinline__ Corr col_corr(int sr, int sm) {
   return Corr{-8 * (sr + sm), 8 * (sm - sr)};
 }
 
+// K baselines of one lane into vis: (vr[v], vi[v]) into pair b[v] of base
+// (b(i, j) = i N - i (i - 1) / 2 + (j - i)), for the v set in ok, in write
+// mode MODE.
+//
+// WM_ATOMIC64: the pair (re, im), read as the 64-bit integer
+// re + 2^32 (im + [re < 0]), takes one atomic add of vr + 2^32 vi, which is
+// exact; the add moves a borrow between the words exactly when the sign of
+// the real word changes (the returned old value tells), and a 32-bit add on
+// the imaginary word takes it back.  Once every add of a launch has landed,
+// the pair is (sum re, sum im) again, so that work items adding into one
+// baseline cost one wide atomic each instead of two.  All K wide adds issue
+// before the first returned value is needed.
+template <int MODE, int K>
+__device__ __forceinline__ void put_pairs(int32_t* base, const int (&b)[K], const int (&vr)[K],
+                                          const int (&vi)[K], uint32_t ok) {
+  if constexpr (MODE == WM_ATOMIC64) {
+    uint32_t old[K];
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      old[v] = 0u;
+      if (ok & (1u << v)) {
+        const unsigned long long add =
+            ((unsigned long long)(uint32_t)vi[v] << 32) + (unsigned long long)(long long)vr[v];
+        old[v] = (uint32_t)atomicAdd(reinterpret_cast<unsigned long long*>(base + 2 * b[v]), add);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      const int re0 = (int)old[v];
+      const int re1 = (int)(old[v] + (uint32_t)vr[v]);
+      const int fix = (re1 < 0) - (re0 < 0);
+      if ((ok & (1u << v)) && fix) atomicAdd(base + 2 * b[v] + 1, fix);
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      if (!(ok & (1u << v))) continue;
+      int32_t* p = base + 2 * b[v];
+      if constexpr (MODE == WM_STORE) {
+        *reinterpret_cast<int2*>(p) = make_int2(vr[v], vi[v]);
+      } else if constexpr (MODE == WM_ADD) {
+        const int2 q = *reinterpret_cast<int2*>(p);
+        *reinterpret_cast<int2*>(p) = make_int2(q.x + vr[v], q.y + vi[v]);
+      } else {
+        atomicAdd(p, vr[v]);
+        if (vi[v]) atomicAdd(p + 1, vi[v]);
+      }
+    }
+  }
+}
+
+// The mode a work item writes in: its int32 atomic adds become one 64-bit
+// atomic per baseline where vis is 8-byte aligned (every channel's and gate's
+// triangle then is).
+__device__ __forceinline__ int wide_atomics(int mode, const int32_t* vis) {
+  return mode == WM_ATOMIC && !(reinterpret_cast<uintptr_t>(vis) & 7) ? (int)WM_ATOMIC64 : mode;
+}
+
+// Packed index of baseline (i, j), i <= j (unsigned arithmetic: callers also
+// form it for rows past N, whose index they never use).
+__device__ __forceinline__ int pair_index(int i, int j, int N) {
+  return (int)((uint32_t)i * (uint32_t)N - (((uint32_t)i * (uint32_t)(i - 1)) >> 1) +
+               (uint32_t)(j - i));
+}
+
 // Write a wave's finished blocks into the packed triangle, adding the offset
 // corrections (corr: 128 row terms, then 128 column terms, in LDS).  Offsets
 // within a channel are 32-bit (the plan limits N so that 2 N(N+1)/2 < 2^31).
-template <class V>
+template <int MODE, class V>
+__device__ __forceinline__ void write_blocks_m(int32_t* base, int N, int rs0, int cs0, int lr0,
+                                               int lc0, const int2* corr, int lane, int mask,
+                                               V (&re)[2][2], V (&im)[2][2]) {
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab) {
+    const int ai = ab >> 1, bi = ab & 1;
+    if (!(mask & (1 << ab))) continue;
+    const int j = cs0 + 32 * bi + (lane & 31);
+    const int2 cj = corr[128 + lc0 + 32 * bi + (lane & 31)];
+    // two groups of eight registers (fewer live values beside the
+    // accumulators still to be written)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int b[8], vr[8], vi[8];
+      uint32_t ok = 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int v = 8 * h + u;
+        const int di = 32 * ai + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int i = rs0 + di;
+        const int2 ci = corr[lr0 + di];
+        ok |= (uint32_t)(i < N && j < N && j >= i) << u;
+        b[u] = pair_index(i, j, N);
+        vr[u] = to_i32(re[ai][bi][v]) + ci.x + cj.x;
+        vi[u] = (i == j) ? 0 : to_i32(im[ai][bi][v]) + ci.y + cj.y;
+      }
+      put_pairs<MODE>(base, b, vr, vi, ok);
+    }
+  }
+}
+
+// WIDE: 32-bit atomic adds become 64-bit ones where vis allows (see
+// put_pairs).  Only the kernels that take it: the wide path's registers
+// change how the compiler lays out the plain kernel's chunk loop (measured
+// slower there), while the persistent kernel, whose tiles are often split in
+// time, gains.
+template <bool WIDE, class V>
 __device__ __forceinline__ void write_blocks(int32_t* vis, int N, long long NB, int f, int rs0,
                                              int cs0, int lr0, int lc0, const int2* corr,
                                              int lane, int mask, int mode, V (&re)[2][2],
                                              V (&im)[2][2]) {
   int32_t* base = vis + 2 * (long long)f * NB;
+  if (WIDE && wide_atomics(mode, vis) == WM_ATOMIC64) {
+    write_blocks_m<WM_ATOMIC64>(base, N, rs0, cs0, lr0, lc0, corr, lane, mask, re, im);
+    return;
+  }
+  // stores, read-add-stores and 32-bit atomics one baseline at a time (the
+  // fewest live registers: the chunk loop keeps its allocation)
 #pragma unroll
   for (int ab = 0; ab < 4; ++ab) {
     const int ai = ab >> 1, bi = ab & 1;
@@ -412,9 +520,7 @@ __device__ __forceinline__ void write_blocks(int32_t* vis, int N, long long NB, 
       const int i = rs0 + di;
       if (i < N && j < N && j >= i) {
         const int2 ci = corr[lr0 + di];
-        // b(i, j) = i N - i (i - 1) / 2 + (j - i)
-        const int b = i * N - ((i * (i - 1)) >> 1) + (j - i);
-        int32_t* p = base + 2 * b;
+        int32_t* p = base + 2 * pair_index(i, j, N);
         const int vr = to_i32(re[ai][bi][v]) + ci.x + cj.x;
         const int vi = (i == j) ? 0 : to_i32(im[ai][bi][v]) + ci.y + cj.y;
         if (mode == WM_STORE) {
@@ -500,8 +606,8 @@ __device__ __forceinline__ void steady_chunks(TileCtx<FORM>& x, int nsteady, int
 }
 
 // The same with one register set: chunk c + 1 loads at the start of chunk
-// c's step and is staged after chunk c's MFMAs.  Sixteen fewer registers,
-// for the persistent kernel, whose two tile paths share one allocation.
+// c's step and is staged after chunk c's MFMAs.  Sixteen fewer registers:
+// for the FP8 form (wider operands) and shifted frames.
 template <int FORM, class R>
 __device__ __forceinline__ void steady_step1(TileCtx<FORM>& x, int cur, int nxt, v4i (&raw)[4],
                                              int ld_chunk) {
@@ -669,15 +775,21 @@ static_assert(2 * EPI_SWAP <= EPI_PART, "epilogue regions overlap");
 // from the history the caller keeps in front of `samples`.  A block's largest
 // delay moves its (scalar) load base back; a lane's offset adds back the rows
 // its own segment is delayed less.  NULL tables: no shift.
-template <int FORM, bool ALIGNED, bool DEEP, bool SHIFT, class Ranges, bool SPLITDIAG = true>
+template <int FORM, bool ALIGNED, bool DEEP, bool SHIFT, class Ranges, bool SPLITDIAG = true,
+          bool WIDE = false>
 __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, int32_t* vis,
                                           int N, long long row_stride, long long NB, int f,
                                           int I, int J, const Ranges& rg, int mode,
                                           uint8_t* lds, const int* seg_delay = nullptr,
                                           const int* blk_delay = nullptr) {
   // the wave index is uniform per wave: read it into a scalar register so that
-  // every branch on it is a uniform one
-  const int tid = threadIdx.x, lane = tid & 63;
+  // every branch on it is a uniform one.  The thread index passes through an
+  // empty asm statement, so that what the tile derives from it is computed
+  // per tile: the persistent kernel would otherwise keep those values live
+  // (and spilled) across its whole loop over tiles.
+  int tid_opaque = threadIdx.x;
+  asm volatile("" : "+v"(tid_opaque));
+  const int tid = tid_opaque, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const bool diag = SPLITDIAG && I == J;  // the split roles of a diagonal tile
   const bool shared = diag && (wave == 1 || wave == 2);  // the shared sub-tile (0, 1)
@@ -720,8 +832,12 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
   x.rowB = 64 * wc;
   x.sm = TileSums{0u, 0u, 0u, 0u};
   // clear this thread's sums slot (it alone adds to it; a wave's LDS
-  // operations complete in order, and the previous tile ended on a barrier)
-  *reinterpret_cast<v4i*>(sum_slot(lds)) = v4i{0, 0, 0, 0};
+  // operations complete in order, and the previous tile ended on a barrier).
+  // The zeros, too, are made per tile (kept across the persistent kernel's
+  // loop, a zero vector would be spilled).
+  int zero = 0;
+  asm volatile("" : "+v"(zero));
+  *reinterpret_cast<v4i*>(sum_slot(lds)) = v4i{zero, zero, zero, zero};
   typedef typename Acc<FORM>::T V;
 #pragma unroll
   for (int p = 0; p < 2; ++p)
@@ -840,7 +956,8 @@ __device__ __forceinline__ void tile_body(const uint8_t* __restrict__ samples, i
     }
   }
   if (mask)
-    write_blocks(vis, N, NB, f, rs0, cs0, 64 * wr, 64 * wc, corr, lane, mask, mode, x.re, x.im);
+    write_blocks<WIDE>(vis, N, NB, f, rs0, cs0, 64 * wr, 64 * wc, corr, lane, mask, mode, x.re,
+                       x.im);
   __syncthreads();  // the corrections are read before the LDS is reused
 }
 

@@ -422,9 +422,7 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
       c.nslices = ns;
       c.slice_len = sl;
       c.row_stride = (long long)F * N;
-      const bool wide_atomics = (reinterpret_cast<uintptr_t>(vis) & 7) == 0;
-      c.write_mode = ns > 1 ? (wide_atomics ? xeng::WM_ATOMIC64 : xeng::WM_ATOMIC)
-                            : (add ? xeng::WM_ADD : xeng::WM_STORE);
+      c.write_mode = ns > 1 ? xeng::WM_ATOMIC : (add ? xeng::WM_ADD : xeng::WM_STORE);
       if (ns > 1 && !add) {
         hipError_t e = xeng::launch_zero(vis, (long long)F * N * (N + 1), s);
         if (e != hipSuccess) return hip_fail(p, e, "zero fill launch");

@@ -8,8 +8,9 @@ namespace xeng {
 
 // How a finished tile reaches vis: plain store, read-add-store (the
 // workgroup owns the tile), or int32 atomic add (several workgroups share it).
-// WM_ATOMIC64 (channel kernel, vis 8-byte aligned): one 64-bit atomic add per
-// baseline instead of two 32-bit ones (see xcorr_chan.hip).
+// Kernels turn WM_ATOMIC into WM_ATOMIC64 where vis is 8-byte aligned: one
+// exact 64-bit atomic add per baseline instead of two 32-bit ones (see
+// put_pairs in xcorr_device.hpp).
 enum WriteMode { WM_STORE = 0, WM_ADD = 1, WM_ATOMIC = 2, WM_ATOMIC64 = 3 };
 
 // Arguments of the tile kernel: one frame, all channels.
@@ -53,7 +54,7 @@ struct ChanArgs {
   int N, F;
   int t0, t1;
   int nslices, slice_len;  // slice_len a multiple of 64
-  int write_mode;          // WM_ATOMIC or WM_ATOMIC64 when nslices > 1
+  int write_mode;          // WM_ATOMIC when nslices > 1
   long long row_stride;    // F * N
 };
 
