@@ -37,7 +37,7 @@ KERNEL_SOURCES = {
     "full_array/f8": ("xcorr_device.hpp", "xcorr_plain.hip", "xcorr_tile.hpp",
                       "xeng_internal.hpp"),
     "full_array/beams16": ("xeng_beam.hip", "xeng_internal.hpp"),
-    "pathfinder/i8": ("xcorr_chan.hip", "xcorr_device.hpp", "xcorr_tile.hpp",
+    "pathfinder/i8": ("xcorr_chan.hip", "xeng_chan.hpp", "xcorr_device.hpp", "xcorr_tile.hpp",
                       "xeng_internal.hpp"),
 }
 

@@ -107,8 +107,12 @@ int xeng_plan(xeng_plan_t *out, int N, int F, int T_max, unsigned flags);
  * "Full Correlation"; Eq. (1)) on the offset-binary samples of Sec. II-A.
  * N and F must equal the plan's, 1 <= T <= T_max.  With XENG_ACCUMULATE in the
  * plan, the frame's sums are added to vis; otherwise vis is overwritten.
+ * The channel kernel (see xeng_plan_set_tuning) with S > 1 time slices keeps
+ * the slices' partial outputs, S F N(N+1) int32, in plan-owned device memory
+ * allocated on first use (grown, after the plan's last call, when S grows).
  * Errors: XENG_EINVAL (NULL plan or pointer, T < 1), XENG_EPLAN (N or F differ
- * from the plan, T > T_max), XENG_EOVERFLOW (T > XENG_T_EXACT_MAX), XENG_EHIP.
+ * from the plan, T > T_max), XENG_EOVERFLOW (T > XENG_T_EXACT_MAX),
+ * XENG_ENOMEM (that memory cannot be allocated), XENG_EHIP.
  */
 int xeng_correlate(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
                    int32_t *vis, void *stream);
@@ -128,9 +132,10 @@ int xeng_correlate(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
  *            always split).  1 chooses the diagonal roles by N (split up to
  *            1024 inputs).  5 = the channel kernel: one workgroup of eight
  *            waves per (channel, time slice) covers the whole triangle of a
- *            channel of at most 256 inputs, each sample read once (int8 form
- *            only; the FP8 form, time shifting through the loads and N > 256
- *            use 1).  Automatic: 5 for the int8 form at 128 < N <= 256 with
+ *            channel of at most 256 inputs, each sample read once; several
+ *            time slices store partial outputs that a second kernel sums
+ *            into vis (int8 form only; the FP8 form, time shifting through
+ *            the loads and N > 256 use 1).  Automatic: 5 for the int8 form at 128 < N <= 256 with
  *            N % 16 == 0 and 16-byte-aligned samples, else 1, the fastest on
  *            gfx950 at the measured sizes; the autotuner (tune.tune_plain)
  *            picks per shape.

@@ -27,8 +27,11 @@
 // with no arithmetic.
 //
 // The workgroup (512 threads, up to 256 registers a thread, 86 KiB of LDS)
-// fills a CU; a launch is one workgroup per (channel, time slice).
+// fills a CU; a launch is one workgroup per (channel, time slice).  With
+// several slices, each stores its own partial triangles and
+// chan_reduce_kernel sums them into vis.
 #include "xcorr_device.hpp"
+#include "xeng_chan.hpp"
 
 namespace xeng {
 
@@ -457,8 +460,8 @@ __device__ __forceinline__ int chan_range(R& role, ChanCtx& x, const uint8_t* sa
 
 // The whole work of one wave role: chunks, sums, epilogue.
 template <bool ALIGNED, class R>
-__device__ __forceinline__ void chan_wave(const ChanArgs& a, int f, int t_begin, int t_end,
-                                          int wave, uint8_t* lds) {
+__device__ __forceinline__ void chan_wave(const ChanArgs& a, int f, int slice, int t_begin,
+                                          int t_end, int wave, uint8_t* lds) {
   const int tid = threadIdx.x, lane = tid & 63;
   R role;
   role.clear();
@@ -492,16 +495,16 @@ __device__ __forceinline__ void chan_wave(const ChanArgs& a, int f, int t_begin,
                        part[1 * CH_IN + tid] + part[3 * CH_IN + tid]);
   __syncthreads();
   const long long NB = (long long)a.N * (a.N + 1) / 2;
-  ChanOut o{a.vis + 2 * (long long)f * NB, a.N, teff, S};
+  int32_t* out = a.partial ? a.partial + 2 * NB * ((long long)slice * a.F) : a.vis;
+  ChanOut o{out + 2 * (long long)f * NB, a.N, teff, S};
   // waves 6 and 7 transpose their diagonal blocks through the (free) stages
   int* m = reinterpret_cast<int*>(lds) + (wave & 1) * 4 * (CH_DIAG / 4);
-  // one dispatch on the (uniform) write mode
-  switch (wide_atomics(a.write_mode, a.vis)) {
-    case WM_STORE: role.template write<WM_STORE>(o, m, lane); break;
-    case WM_ADD: role.template write<WM_ADD>(o, m, lane); break;
-    case WM_ATOMIC64: role.template write<WM_ATOMIC64>(o, m, lane); break;
-    default: role.template write<WM_ATOMIC>(o, m, lane); break;
-  }
+  // one dispatch on the (uniform) write mode: a lone slice stores or adds into
+  // vis, several slices store into their own partial triangles
+  if (a.write_mode == WM_ADD)
+    role.template write<WM_ADD>(o, m, lane);
+  else
+    role.template write<WM_STORE>(o, m, lane);
 }
 
 }  // namespace
@@ -516,15 +519,53 @@ __global__ void __launch_bounds__(CH_THREADS, 1) xcorr_chan_kernel(ChanArgs a) {
   // uniform per wave: the role dispatch is a scalar branch
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   switch (wave) {
-    case 0: chan_wave<ALIGNED, OffRole<0, 1, 0>>(a, f, t_begin, t_end, wave, lds); break;
-    case 1: chan_wave<ALIGNED, OffRole<0, 2, 1>>(a, f, t_begin, t_end, wave, lds); break;
-    case 2: chan_wave<ALIGNED, OffRole<0, 3, 2>>(a, f, t_begin, t_end, wave, lds); break;
-    case 3: chan_wave<ALIGNED, OffRole<1, 2, 0>>(a, f, t_begin, t_end, wave, lds); break;
-    case 4: chan_wave<ALIGNED, OffRole<1, 3, 3>>(a, f, t_begin, t_end, wave, lds); break;
-    case 5: chan_wave<ALIGNED, OffRole<2, 3, 0>>(a, f, t_begin, t_end, wave, lds); break;
-    case 6: chan_wave<ALIGNED, DiagRole<0, 3>>(a, f, t_begin, t_end, wave, lds); break;
-    default: chan_wave<ALIGNED, DiagRole<2, 1>>(a, f, t_begin, t_end, wave, lds); break;
+    case 0: chan_wave<ALIGNED, OffRole<0, 1, 0>>(a, f, s, t_begin, t_end, wave, lds); break;
+    case 1: chan_wave<ALIGNED, OffRole<0, 2, 1>>(a, f, s, t_begin, t_end, wave, lds); break;
+    case 2: chan_wave<ALIGNED, OffRole<0, 3, 2>>(a, f, s, t_begin, t_end, wave, lds); break;
+    case 3: chan_wave<ALIGNED, OffRole<1, 2, 0>>(a, f, s, t_begin, t_end, wave, lds); break;
+    case 4: chan_wave<ALIGNED, OffRole<1, 3, 3>>(a, f, s, t_begin, t_end, wave, lds); break;
+    case 5: chan_wave<ALIGNED, OffRole<2, 3, 0>>(a, f, s, t_begin, t_end, wave, lds); break;
+    case 6: chan_wave<ALIGNED, DiagRole<0, 3>>(a, f, s, t_begin, t_end, wave, lds); break;
+    default: chan_wave<ALIGNED, DiagRole<2, 1>>(a, f, s, t_begin, t_end, wave, lds); break;
   }
+}
+
+// The slices' partial triangles summed into vis: one pass over HBM, which
+// costs less than the slices adding into vis with atomics after a fill (every
+// workgroup of the channel kernel finishes at once, so nothing would hide the
+// atomics).
+__global__ void chan_reduce_kernel(const int32_t* __restrict__ part, int32_t* __restrict__ vis,
+                                   long long n, int ns, int add) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((n & 3) == 0 && !(reinterpret_cast<uintptr_t>(vis) & 15)) {
+    const long long n4 = n >> 2;
+    const v4i* p4 = reinterpret_cast<const v4i*>(part);
+    v4i* v4 = reinterpret_cast<v4i*>(vis);
+    for (; i < n4; i += stride) {
+      v4i acc = p4[i];
+      for (int s = 1; s < ns; ++s) acc += p4[s * n4 + i];
+      if (add) acc += v4[i];
+      v4[i] = acc;
+    }
+  } else {
+    for (; i < n; i += stride) {
+      int acc = part[i];
+      for (int s = 1; s < ns; ++s) acc += part[s * n + i];
+      vis[i] = add ? vis[i] + acc : acc;
+    }
+  }
+}
+
+hipError_t launch_chan_reduce(const int32_t* partial, int32_t* vis, long long n, int ns, bool add,
+                              hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  if (ns < 1) return hipErrorInvalidValue;
+  long long blocks = ((n >> 2) + 255) / 256;
+  blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+  hipLaunchKernelGGL(chan_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, partial,
+                     vis, n, ns, add ? 1 : 0);
+  return hipGetLastError();
 }
 
 hipError_t launch_chan(const ChanArgs& a, bool aligned, hipStream_t stream) {

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "xeng_chan.hpp"
 #include "xeng_internal.hpp"
 #include "xeng_noalloc.hpp"
 
@@ -76,6 +77,13 @@ struct xeng_plan_s {
   std::vector<int> gate_count, gate_fill;  // host work space of the run tables, G_max each
   std::vector<int> gate_zero;              // gates to clear before a split gate adds into them
   std::vector<int> seg_goff, seg_nvg;      // per launch segment: first table entry, work gates
+
+  // channel kernel with time slices: the slices' partial triangles (plan-owned,
+  // grown on demand) and the event of the last call that read them
+  int32_t* d_chan_ws = nullptr;
+  size_t chan_ws_ints = 0;
+  hipEvent_t chan_ws_used = nullptr;
+  bool chan_ws_pending = false;
 
   // time shifting (xeng_plan_set_delays): per-segment delays and block maxima
   bool shift = false;
@@ -366,6 +374,39 @@ int xeng_plan_set_tuning(xeng_plan_t p, int split_t, int kernel) {
 
 const char* xeng_plan_error(xeng_plan_t p) { return p ? p->err.c_str() : ""; }
 
+// The channel kernel's slice workspace, at least `ints` int32: grown when
+// needed (after the plan's last call that read it has finished), and ordered
+// after that call on `s` when it may still run on another stream.
+static int chan_workspace(xeng_plan_t p, size_t ints, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (!p->chan_ws_used) {
+    e = hipEventCreateWithFlags(&p->chan_ws_used, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(p, e, "hipEventCreate");
+  }
+  if (ints > p->chan_ws_ints) {
+    if (p->chan_ws_pending) {
+      e = hipEventSynchronize(p->chan_ws_used);
+      if (e != hipSuccess) return hip_fail(p, e, "hipEventSynchronize");
+      p->chan_ws_pending = false;
+    }
+    if (p->d_chan_ws) (void)hipFree(p->d_chan_ws);
+    p->d_chan_ws = nullptr;
+    p->chan_ws_ints = 0;
+    e = hipMalloc((void**)&p->d_chan_ws, ints * sizeof(int32_t));
+    if (e != hipSuccess) {
+      p->d_chan_ws = nullptr;
+      (void)hipGetLastError();
+      if (e == hipErrorOutOfMemory) return XENG_ENOMEM;
+      return hip_fail(p, e, "hipMalloc (slice workspace)");
+    }
+    p->chan_ws_ints = ints;
+  } else if (p->chan_ws_pending) {
+    e = hipStreamWaitEvent(s, p->chan_ws_used, 0);
+    if (e != hipSuccess) return hip_fail(p, e, "hipStreamWaitEvent");
+  }
+  return XENG_OK;
+}
+
 int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, int32_t* vis,
                    void* stream) {
   if (!p || !samples || !vis || N < 1 || F < 1 || T < 1) return XENG_EINVAL;
@@ -412,6 +453,11 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
       sl = (sl + kChunk - 1) / kChunk * kChunk;
       ns = (len + sl - 1) / sl;
       const bool add = p->accumulate || t0 > 0;
+      const long long part = (long long)F * N * (N + 1);  // ints of one slice's triangles
+      if (ns > 1) {
+        rc = chan_workspace(p, (size_t)ns * (size_t)part, s);
+        if (rc != XENG_OK) return rc;
+      }
       xeng::ChanArgs c;
       c.samples = samples;
       c.vis = vis;
@@ -422,13 +468,19 @@ int xeng_correlate(xeng_plan_t p, const uint8_t* samples, int N, int F, int T, i
       c.nslices = ns;
       c.slice_len = sl;
       c.row_stride = (long long)F * N;
-      c.write_mode = ns > 1 ? xeng::WM_ATOMIC : (add ? xeng::WM_ADD : xeng::WM_STORE);
-      if (ns > 1 && !add) {
-        hipError_t e = xeng::launch_zero(vis, (long long)F * N * (N + 1), s);
-        if (e != hipSuccess) return hip_fail(p, e, "zero fill launch");
-      }
+      // one slice writes vis itself; several store their own triangles into
+      // the workspace, and a second kernel sums them into vis
+      c.partial = ns > 1 ? p->d_chan_ws : nullptr;
+      c.write_mode = (ns == 1 && add) ? xeng::WM_ADD : xeng::WM_STORE;
       hipError_t e = xeng::launch_chan(c, aligned, s);
       if (e != hipSuccess) return hip_fail(p, e, "channel kernel launch");
+      if (ns > 1) {
+        e = xeng::launch_chan_reduce(p->d_chan_ws, vis, part, ns, add, s);
+        if (e != hipSuccess) return hip_fail(p, e, "slice sum launch");
+        e = hipEventRecord(p->chan_ws_used, s);
+        if (e != hipSuccess) return hip_fail(p, e, "hipEventRecord");
+        p->chan_ws_pending = true;
+      }
       continue;
     }
     const long long W = tpc * F;  // tiles of the launch
@@ -1179,6 +1231,8 @@ int xeng_destroy(xeng_plan_t p) {
   if (p->d_seg_delay) (void)hipFree(p->d_seg_delay);
   if (p->d_blk_delay) (void)hipFree(p->d_blk_delay);
   if (p->d_shifted) (void)hipFree(p->d_shifted);
+  if (p->d_chan_ws) (void)hipFree(p->d_chan_ws);
+  if (p->chan_ws_used) (void)hipEventDestroy(p->chan_ws_used);
   if (p->d_fU) (void)hipFree(p->d_fU);
   if (p->d_fX) (void)hipFree(p->d_fX);
   if (p->d_fint) (void)hipFree(p->d_fint);

@@ -8,9 +8,9 @@ namespace xeng {
 
 // How a finished tile reaches vis: plain store, read-add-store (the
 // workgroup owns the tile), or int32 atomic add (several workgroups share it).
-// Kernels turn WM_ATOMIC into WM_ATOMIC64 where vis is 8-byte aligned: one
-// exact 64-bit atomic add per baseline instead of two 32-bit ones (see
-// put_pairs in xcorr_device.hpp).
+// The persistent batch kernel turns WM_ATOMIC into WM_ATOMIC64 where vis is
+// 8-byte aligned: one exact 64-bit atomic add per baseline instead of two
+// 32-bit ones (see put_pairs in xcorr_device.hpp).
 enum WriteMode { WM_STORE = 0, WM_ADD = 1, WM_ATOMIC = 2, WM_ATOMIC64 = 3 };
 
 // Arguments of the tile kernel: one frame, all channels.
@@ -44,22 +44,6 @@ struct TileArgs {
 };
 
 hipError_t launch_tiles(const TileArgs& a, int form, bool aligned, hipStream_t stream);
-
-// Arguments of the channel kernel (int8, N <= 256): one workgroup per
-// (channel f, time slice s), integrating [t0 + s slice_len, ...) within
-// [t0, t1) into the whole triangle of channel f.
-struct ChanArgs {
-  const uint8_t* samples;  // device [T][F][N]
-  int32_t* vis;            // device [F][N(N+1)/2][2]
-  int N, F;
-  int t0, t1;
-  int nslices, slice_len;  // slice_len a multiple of 64
-  int write_mode;          // WM_ATOMIC when nslices > 1
-  long long row_stride;    // F * N
-};
-
-// aligned: fast 16-byte loads (N % 16 == 0, 16-byte aligned rows, F N <= 2^25)
-hipError_t launch_chan(const ChanArgs& a, bool aligned, hipStream_t stream);
 
 // Output gating: every (channel, tile, work gate g) integrates the runs
 // runs[gate_off[g] .. gate_off[g + 1]) (absolute [begin, end) sample ranges)

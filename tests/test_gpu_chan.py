@@ -75,8 +75,8 @@ def test_chan_accumulate(split):
 
 @pytest.mark.parametrize("split,offset", [(1, 4096), (5, 4096), (5, 4097)])
 def test_chan_writes_only_its_triangle(split, offset):
-    # offset 4097: vis only 4-byte aligned, so time slices add with 32-bit
-    # atomics instead of the 64-bit ones
+    # offset 4097: vis only 4-byte aligned (the slices' sum takes the
+    # word-by-word path)
     T, F, N = 900, 3, 256
     s = rand_frame(73, T, F, N)
     n = F * N * (N + 1)
@@ -94,9 +94,8 @@ def test_chan_writes_only_its_triangle(split, offset):
 
 @pytest.mark.parametrize("split", [2, 3, 16])
 def test_chan_slices_cross_zero(split):
-    # time slices whose partial real parts have opposite signs: the 64-bit
-    # atomic adds move borrows between the words, which the fix-ups undo;
-    # accumulating onto negative and positive starting values as well
+    # time slices whose partial real parts have opposite signs, summed into vis
+    # by the second kernel, also onto negative and positive starting values
     T, F, N = 64 * 48, 2, 200
     s = rand_frame(78, T, F, N)
     s[: T // 2] = 0x00            # -8-8i: large positive real parts

@@ -380,3 +380,40 @@ def test_batch_accumulate_time_additivity():
         torch.cuda.synchronize()
     for v, k in zip(vis, keep):
         assert np.array_equal(v.cpu().numpy(), want(frames[k])), k
+
+
+@pytest.mark.parametrize("offset", [4096, 4097])
+def test_batch_slices_cross_zero_and_alignment(offset):
+    # time-sliced instances whose partial real parts change sign from slice to
+    # slice, accumulated onto starting values of both signs: with vis 8-byte
+    # aligned (offset 4096) the slices add with 64-bit atomics, whose borrows
+    # between the words the fix-ups undo; at offset 4097 (4-byte aligned) with
+    # 32-bit atomics.  Nothing outside the outputs is written.
+    insts = [(200, 2, 64 * 48), (72, 3, 64 * 30 + 7)]
+    frames = []
+    for k, (N, F, T) in enumerate(insts):
+        s = rand_frame(90 + k, T, F, N)
+        s[: T // 2] = 0x00            # -8-8i: large positive real parts
+        s[T // 2:, :, ::2] = 0xF0     # 7-8i against -8-8i: negative real parts
+        s[T // 2:, :, 1::2] = 0x00
+        frames.append(s)
+    sizes = [F * N * (N + 1) for N, F, T in insts]
+    sentinel = 0x5EADBEEF
+    bufs, vis, starts = [], [], []
+    rng = np.random.default_rng(91)
+    for (N, F, T), n in zip(insts, sizes):
+        buf = torch.full((n + 2 * 4097,), sentinel, dtype=torch.int32, device=DEV)
+        start = rng.integers(-5_000_000, 5_000_000, n).astype(np.int32)
+        v = buf[offset:offset + n]
+        v.copy_(torch.from_numpy(start).to(DEV))
+        bufs.append(buf)
+        starts.append(start.reshape(engine.vis_shape(N, F)))
+        vis.append(v.view(engine.vis_shape(N, F)))
+    d = [torch.from_numpy(s).to(DEV) for s in frames]
+    with BatchPlan(insts, accumulate=True, split_t=[3, 5]) as bp:
+        bp.correlate(d, vis)
+        torch.cuda.synchronize()
+    for k, s in enumerate(frames):
+        assert np.array_equal(vis[k].cpu().numpy(), want(s) + starts[k]), k
+        h = bufs[k].cpu().numpy()
+        assert (h[:offset] == sentinel).all() and (h[offset + sizes[k]:] == sentinel).all()
