@@ -6,10 +6,10 @@
 // Work split.  The 256 inputs form eight 32-input fragments (one MFMA block
 // edge) and four 64-input quarters q = 0..3; quarter q lies in block q / 2 of
 // the stage at column 64 (q % 2).  The triangle holds 28 blocks off the
-// diagonal and 8 on it.  An off-diagonal block takes two accumulators (Re and Im, as in the
-// tile kernels); a diagonal block takes one (see DiagRole), so the channel is
-// 28 x 2 + 8 = 64 accumulators of 16 registers, eight per wave, and every wave
-// issues the same number of MFMAs:
+// diagonal and 8 on it.  An off-diagonal block takes two accumulators (Re and
+// Im, as in the tile kernels); a diagonal block takes one (see DiagRole), so
+// the channel is 28 x 2 + 8 = 64 accumulators of 16 registers, eight per
+// wave, and every wave issues the same number of MFMAs:
 //
 //   waves 0..5  the six off-diagonal 64 x 64 quarter pairs (QA, QB), QA < QB,
 //               2 x 2 blocks each (OffRole);
