@@ -158,3 +158,28 @@ def test_chan_rejected_outside_its_range():
         got = p.correlate(d)
         torch.cuda.synchronize()
     assert np.array_equal(got.cpu().numpy(), want(d.cpu().numpy()))
+
+
+def test_chan_workspace_grows_and_orders_streams():
+    # the slices' workspace grows with the slice count (after the plan's last
+    # call) and is reused when it shrinks; calls on another stream wait for
+    # the previous call's sum before overwriting it
+    T, F, N = 4133, 2, 256
+    a, b = rand_frame(80, T, F, N), rand_frame(81, T, F, N)
+    da, db = torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV)
+    wa, wb = want(a), want(b)
+    with Plan(N, F, T, split_t=2, kernel=5) as p:
+        assert np.array_equal(p.correlate(da).cpu().numpy(), wa)
+        for split in (7, 3, 16):
+            p.set_tuning(split, 5)
+            assert np.array_equal(p.correlate(db).cpu().numpy(), wb), split
+        s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+        v1 = torch.empty_like(torch.from_numpy(wa)).to(DEV)
+        v2 = torch.empty_like(v1)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            p.correlate(da, v1, stream=s1)
+            p.correlate(db, v2, stream=s2)
+        torch.cuda.synchronize()
+        assert np.array_equal(v1.cpu().numpy(), wa)
+        assert np.array_equal(v2.cpu().numpy(), wb)
