@@ -121,7 +121,8 @@ int xeng_correlate(xeng_plan_t p, const uint8_t *samples, int N, int F, int T,
  * Tuning knobs of a plan (0 = choose automatically):
  *   split_t  number of time slices per tile (1 = one workgroup per tile; more
  *            slices fill the GPU when there are few tiles, at the price of
- *            int32 atomic adds into vis, which are exact);
+ *            exact integer atomic adds into vis, or, for the channel kernel,
+ *            of partial outputs summed by a second kernel);
  *   kernel   tile shape: 1 = 128 x 128 baselines per workgroup (two
  *            workgroups per CU), 2 = 128 x 256 (one per CU; used only when
  *            N % 16 == 0 and the samples are 16-byte aligned, else 1),

@@ -14,7 +14,7 @@ Batched form (``tune``):
 A batched plan launches one persistent kernel over the tiles of every
 instance.  Splitting an instance's integration into several time slices gives
 the scheduler more, smaller work items (better load balance across uneven N),
-at the price of exact int32 atomic adds into vis and a clear beforehand.  For
+at the price of exact integer atomic adds into vis and a clear beforehand.  For
 every distinct shape (N, F, T) of a batch, the tuner times candidate splits on
 a batch that holds as many copies of that shape as the real batch does, on
 seeded synthetic frames, rejects any candidate whose output is not bit-identical
