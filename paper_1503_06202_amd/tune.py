@@ -2,10 +2,11 @@
 per instance shape of a batched plan.
 
 Plain form (``tune_plain``): for one frame shape (N, F, T) the tuner times
-every tile shape the library has on seeded synthetic frames of that shape:
+every kernel shape the library has on seeded synthetic frames of that shape:
+the channel kernel (kernel 5 of ``xeng_plan_set_tuning``; int8, N <= 256),
 128 x 128 tiles with split or common wave roles in diagonal tiles (kernel 3
-or 4 of ``xeng_plan_set_tuning``) and 128 x 256 tiles (kernel 2), each with
-the automatic time slices and with 1, 2 and 4 slices.  It rejects any
+or 4) and 128 x 256 tiles (kernel 2), each with the automatic time slices and
+with 1, 2 and 4 slices.  It rejects any
 candidate whose output is not bit-identical to the first candidate's, keeps
 the fastest, and caches it as JSON keyed by (arch, form, N, F, T).
 
