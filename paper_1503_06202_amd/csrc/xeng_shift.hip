@@ -10,9 +10,14 @@
 //     dst[t][f][16 g + e] = src[t - d_g][f][16 g + e],   0 <= t < T,
 //
 // where rows t - d_g < 0 are the history before src; the correlation then
-// reads the copy with no delay.  One thread per 16-input piece: consecutive
-// threads write consecutive pieces of a row (whole lines) and read each piece
-// from its own delayed row.
+// reads the copy with no delay.  One thread per 16-input piece.  Every
+// 16-byte read fetches a whole 128-byte line, whose other seven pieces the
+// copy needs again at other output rows, up to the largest delay later.  The
+// copy therefore runs over one line column (eight groups of one channel) at a
+// time, all output rows of the column together: eight neighbouring threads
+// write one output line, and a line read for one group of the column is
+// more often still cached (in the memory-side cache) when the column's other
+// groups read it than when every channel's rows are copied in turn.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,13 +31,19 @@ __global__ void __launch_bounds__(256) shift_copy_kernel(const uint8_t* __restri
                                                          uint8_t* __restrict__ dst, int N, int F,
                                                          int T, const int* __restrict__ seg_delay) {
   const int P = (N + 15) / 16;
-  const long long total = (long long)T * F * P;
+  const int C = (P + 7) / 8;  // line columns of a channel
+  // e = ((f C + c) T + t) 8 + g: piece p = 8 c + g of row t of channel f
+  const long long total = (long long)F * C * T * 8;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
-    const int p = (int)(e % P);
-    const long long tf = e / P;  // t F + f
-    const long long from = (tf - (long long)seg_delay[p] * F) * N + 16 * p;
-    const long long to = tf * N + 16 * p;
+    const int g = (int)(e & 7);
+    const long long rest = e >> 3;
+    const long long t = rest % T, fc = rest / T;
+    const int c = (int)(fc % C), f = (int)(fc / C);
+    const int p = 8 * c + g;
+    if (p >= P) continue;  // the last column of a channel whose N is not a multiple of 128
+    const long long from = ((t - seg_delay[p]) * F + f) * N + 16 * p;
+    const long long to = (t * F + f) * N + 16 * p;
     if (VEC) {
       *reinterpret_cast<uint4*>(dst + to) = *reinterpret_cast<const uint4*>(src + from);
     } else {
@@ -46,7 +57,7 @@ __global__ void __launch_bounds__(256) shift_copy_kernel(const uint8_t* __restri
 
 hipError_t launch_shift_copy(const uint8_t* src, uint8_t* dst, int N, int F, int T,
                              const int* seg_delay, hipStream_t stream) {
-  const long long total = (long long)T * F * ((N + 15) / 16);
+  const long long total = (long long)F * ((N + 127) / 128) * T * 8;
   if (total <= 0) return hipSuccess;
   long long blocks = (total + 255) / 256;
   if (blocks > 16384) blocks = 16384;

@@ -417,3 +417,58 @@ def test_batch_slices_cross_zero_and_alignment(offset):
         assert np.array_equal(vis[k].cpu().numpy(), want(s) + starts[k]), k
         h = bufs[k].cpu().numpy()
         assert (h[:offset] == sentinel).all() and (h[offset + sizes[k]:] == sentinel).all()
+
+
+# Batches that leave their time slices to the library and hold a few more tiles
+# than the GPU has workgroup slots: on a 256-CU GPU (512 slots) the 672 tiles
+# of BIG_MIX take 3 automatic slices and the 576 of BIG_SAME 4 (cost model of
+# the automatic slice count), so every tile adds its slices with atomics into a
+# cleared output, or into the caller's accumulator.
+BIG_MIX = [(1024, 12, 8192), (640, 16, 8192)]
+BIG_SAME = [(1024, 8, 8192), (1024, 8, 8192)]
+
+
+@pytest.fixture(scope="module")
+def big_batch_frames():
+    frames = {}
+    for name, insts in (("mix", BIG_MIX), ("same", BIG_SAME)):
+        frames[name] = [rand_frame(120 + 10 * len(frames) + k, T, F, N)
+                        for k, (N, F, T) in enumerate(insts)]
+    ref = {name: [want(s) for s in fr] for name, fr in frames.items()}
+    return frames, ref
+
+
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_batch_more_tiles_than_slots(big_batch_frames, accumulate):
+    frames, ref = big_batch_frames
+    d = [torch.from_numpy(s).to(DEV) for s in frames["mix"]]
+    rng = np.random.default_rng(130)
+    starts = [rng.integers(-1_000_000, 1_000_000, engine.vis_shape(N, F)).astype(np.int32)
+              if accumulate else np.full(engine.vis_shape(N, F), -7, np.int32)
+              for N, F, T in BIG_MIX]
+    vis = [torch.from_numpy(s).to(DEV) for s in starts]
+    with BatchPlan(BIG_MIX, accumulate=accumulate) as bp:
+        for rep in range(2):  # eager, then a graph replay
+            if rep:
+                for v, s in zip(vis, starts):
+                    v.copy_(torch.from_numpy(s).to(DEV))
+            bp.correlate(d, vis, graph=bool(rep))
+            torch.cuda.synchronize()
+            for k in range(len(BIG_MIX)):
+                exp = ref["mix"][k] + (starts[k] if accumulate else 0)
+                assert np.array_equal(vis[k].cpu().numpy(), exp), (rep, k)
+
+
+def test_batch_more_tiles_than_slots_shared_vis(big_batch_frames):
+    # two frames of one shape adding into one accumulator, as the request
+    # loop's launches do
+    frames, ref = big_batch_frames
+    d = [torch.from_numpy(s).to(DEV) for s in frames["same"]]
+    N, F, T = BIG_SAME[0]
+    start = np.random.default_rng(131).integers(-1_000_000, 1_000_000,
+                                                engine.vis_shape(N, F)).astype(np.int32)
+    acc = torch.from_numpy(start).to(DEV)
+    with BatchPlan(BIG_SAME, accumulate=True, shared_vis=True) as bp:
+        bp.correlate(d, [acc, acc], graph=True)
+        torch.cuda.synchronize()
+    assert np.array_equal(acc.cpu().numpy(), ref["same"][0] + ref["same"][1] + start)

@@ -60,7 +60,7 @@ def rand_ext(seed, TT, F, N):
 
 
 @pytest.mark.parametrize("form", ["i8", "f8"])
-@pytest.mark.parametrize("N", [96, 40])
+@pytest.mark.parametrize("N", [96, 40, 144, 300])
 def test_group_delays(form, N):
     D, T, F = 300, 700 + 5, 2
     ext = rand_ext(61 + N, D + T, F, N)
