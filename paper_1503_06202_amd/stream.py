@@ -12,11 +12,15 @@ one in-flight frame) is free; whenever fewer than ``max_inflight`` launches
 are on the GPU, the admitted frames not yet launched (up to the launcher's
 ``max_batch``) go out in one batched launch, so frames that arrive while
 others run are picked up at the next launch instead of waiting for a drained
-queue.  The GPU launcher alternates launches over two HIP streams, so that a
-launch fills the compute units the previous one leaves idle as it drains.
-Frames of one stream may share a launch, and launches on both HIP streams add
-into the same accumulator: the batched kernels add with exact int32 atomics,
-whose order does not matter.  Latency is measured from a frame's arrival to
+queue.  Two launches are in flight by default: the GPU launcher queues them
+on one HIP stream, so the second starts on the device as soon as the first
+ends, while the host forms the next batch.  It can also spread launches over
+several HIP streams (``queues``), where a launch fills the compute units the
+previous one leaves idle as it drains; on full-size frames two concurrent
+batched kernels served fewer frames per second than two queued launches, and
+with a longer p99.  Frames of one stream may share a launch, and launches on
+any HIP stream add into the same accumulator: the batched kernels add with
+exact int32 atomics, whose order does not matter.  Latency is measured from a frame's arrival to
 the completion of the launch that carried it.
 
 The loop talks to a launcher (``launch``, ``ready``, ``dump``); the GPU
@@ -92,7 +96,7 @@ class RequestLoop:
                  clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep):
         if max_inflight is None:
-            max_inflight = getattr(launcher, "queues", 2)
+            max_inflight = 2  # the next launch waits on the device, not on the host
         if launcher.slots < 1 or max_inflight < 1 or dump_every < 1:
             raise ValueError("slots, max_inflight and dump_every must be >= 1")
         self.launcher = launcher
@@ -160,8 +164,10 @@ class RequestLoop:
                         dumps.append((st, counts[st], self.launcher.dump(st)))
                         counts[st] = 0
                 continue
-            if not (waiting and used < slots) and not admitted:
-                # idle until the next arrival or completion
+            blocked = bool(admitted) and len(inflight) >= self.max_inflight
+            if blocked or (not (waiting and used < slots) and not admitted):
+                # idle until the next arrival or completion (admitted frames
+                # waiting for a launch slot wait for a completion too)
                 if inflight:
                     self.launcher.poll_wait(inflight[0][0])
                 elif arriving:
@@ -189,12 +195,15 @@ class GpuLauncher:
     """Runs batches of frames of one shape through ``libxeng.so``.
 
     Launches go to an idle one of ``queues`` HIP streams (default priority),
-    else to the next in turn, so that a launch starts filling the compute
-    units while the previous one drains and never queues behind a long launch
-    while another HIP stream is free.
+    else to the next in turn.  With one HIP stream (the default) launches run
+    one after another on the device, the next queued behind the current one;
+    with several, a launch starts filling the compute units while the
+    previous one drains (measured slower on full-size frames than two
+    launches in a row on one stream).
     Each HIP stream has its own batched plans, one per batch size k =
-    1..``max_batch`` (k identical instances (N, F, T)), because a plan takes
-    one call at a time; a plan's automatic time slices are chosen for k
+    1..``max_batch`` (k identical instances (N, F, T)), because a plan's calls
+    must not overlap on the device (calls on one HIP stream run in order); a
+    plan's automatic time slices are chosen for k
     frames' worth of tiles, so that a lone frame spreads over the whole GPU
     as well as a full batch does.  Every stream's accumulator lives on the
     GPU; frames add into it (shared, atomic) from either HIP stream.  ``dump``
@@ -208,7 +217,7 @@ class GpuLauncher:
 
     def __init__(self, N: int, F: int, T: int, slots: Optional[int] = None, streams: int = 1,
                  form: str = "i8", graph: bool = True, device=None, max_batch: int = 8,
-                 queues: int = 2, dump_buffers: int = 4):
+                 queues: int = 1, dump_buffers: int = 4):
         import torch
 
         from .engine import BatchPlan, vis_shape

@@ -10,8 +10,10 @@ from paper_1503_06202_amd.stream import Frame, GpuLauncher, RequestLoop, poisson
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_request_loop_accumulates_exactly(graph):
+@pytest.mark.parametrize("graph,queues", [(False, 1), (True, 1), (True, 2)])
+def test_request_loop_accumulates_exactly(graph, queues):
+    # one HIP stream with two launches queued (the default), or launches on
+    # two HIP streams adding into the same accumulators
     N, F, T, streams = 136, 2, 320, 3
     rng = np.random.default_rng(17)
     host = [rng.integers(0, 256, (T, F, N), dtype=np.uint8) for _ in range(12)]
@@ -20,7 +22,7 @@ def test_request_loop_accumulates_exactly(graph):
     arr = poisson_arrivals(n, 4000.0, 5)
     frames = [Frame(k, k % streams, pool[k % len(pool)], float(arr[k])) for k in range(n)]
     la = GpuLauncher(N, F, T, slots=4, streams=streams, graph=graph, max_batch=4,
-                     dump_buffers=16)
+                     dump_buffers=16, queues=queues)
     rep = RequestLoop(la, dump_every=5).run(frames)
     torch.cuda.synchronize()
     assert rep.frames == n and max(rep.batch_sizes) <= 4

@@ -157,3 +157,63 @@ def test_checkpoint_and_resume_dump_like_an_uninterrupted_run():
     assert second.pending == whole.pending
     for st in (0, 1):
         assert np.array_equal(np.asarray(la2.acc[st]), np.asarray(la.acc[st]))
+
+
+def single_server_latencies(arrivals, service, max_inflight, max_batch):
+    """Latency of every frame (arrival order) under the loop's policy, as a
+    plain event recursion: whenever fewer than ``max_inflight`` launches are
+    outstanding, every waiting frame (at most ``max_batch``) goes out in one
+    launch; launches are served one after another, a launch of k frames
+    taking service(k) seconds."""
+    n, lat = len(arrivals), [0.0] * len(arrivals)
+    waiting, i, t, free, outstanding = collections.deque(), 0, 0.0, 0.0, []
+    while i < n or waiting:
+        outstanding = [c for c in outstanding if c > t]
+        while i < n and arrivals[i] <= t:
+            waiting.append(i)
+            i += 1
+        if waiting and len(outstanding) < max_inflight:
+            batch = [waiting.popleft() for _ in range(min(len(waiting), max_batch))]
+            done = max(t, free) + service(len(batch))
+            free = done
+            outstanding.append(done)
+            for k in batch:
+                lat[k] = done - arrivals[k]
+            continue
+        t = min(outstanding + ([arrivals[i]] if i < n else []))
+    return np.array(lat)
+
+
+class ExactLauncher(FakeLauncher):
+    """Waits until the next completion or arrival, whichever comes first, so
+    that the loop sees every event at its exact time."""
+
+    def __init__(self, clock, arrivals, max_batch, **kw):
+        super().__init__(clock, **kw)
+        self.arrivals = np.sort(np.asarray(arrivals))
+        self.max_batch = max_batch  # the loop's batch cap, as GpuLauncher sets it
+
+    def poll_wait(self, token):
+        k = int(np.searchsorted(self.arrivals, self.clock.t, side="right"))
+        nxt = self.arrivals[k] if k < len(self.arrivals) else float("inf")
+        self.clock.t = max(self.clock.t, min(token[0], nxt))
+
+
+@pytest.mark.parametrize("max_inflight", [1, 2])
+def test_loop_matches_single_server_model(max_inflight):
+    # launch times close to the GPU's for the stream frames (a fixed 0.07 ms
+    # plus 0.78 ms a frame), arrivals at 0.9 of the batch-of-8 rate: the loop
+    # adds no delay to what the policy itself implies
+    fixed, per = 0.07e-3, 0.78e-3
+    rate = 0.9 * 8 / (fixed + 8 * per)
+    fr = frames_for(1500, 1, rate=rate, seed=5, N=4, F=1, T=4)
+    arrivals = [f.arrival for f in fr]
+    clk = VClock()
+    la = ExactLauncher(clk, arrivals, 8, slots=10_000, service_s=fixed, per_frame_s=per)
+    rep = RequestLoop(la, max_inflight=max_inflight, dump_every=10_000, clock=clk,
+                      sleep=clk.sleep).run(fr)
+    assert rep.frames == len(fr)
+    got = np.array([f.done - f.arrival for f in fr])
+    want = single_server_latencies(arrivals, lambda k: fixed + per * k, max_inflight, 8)
+    assert np.allclose(got, want, rtol=0, atol=1e-9)
+    assert np.percentile(got, 99) > 5 * (fixed + per)  # a loaded queue, not an idle one
