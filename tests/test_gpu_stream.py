@@ -111,12 +111,15 @@ def test_tuner_choices_are_exact(tmp_path):
         assert np.array_equal(v.cpu().numpy(), oracle.to_int32(oracle.correlate(h)))
 
 
-def test_plain_tuner_picks_an_exact_tile_shape(tmp_path):
-    N, F, T = 384, 4, 2048
+@pytest.mark.parametrize("N,F,T", [(384, 4, 2048), (200, 8, 4096)])
+def test_plain_tuner_picks_an_exact_tile_shape(tmp_path, N, F, T):
+    # at N <= 256 the channel kernel (kernel 5) is among the timed candidates
     path = str(tmp_path / "tune.json")
     kernel, split = tune.tune_plain(N, F, T, reps=2, cache_path=path)
     assert kernel in tune.PLAIN_KERNELS and split in tune.PLAIN_SPLITS
     assert tune.tune_plain(N, F, T, reps=2, cache_path=path) == (kernel, split)  # cached
+    timed = {k.split("/")[0] for k in next(iter(tune.load_cache(path).values()))["ms"]}
+    assert ("5" in timed) == (N <= 256)
     s = np.random.default_rng(9).integers(0, 256, (T, F, N), dtype=np.uint8)
     with Plan(N, F, T, split_t=split, kernel=kernel) as p:
         got = p.correlate(torch.from_numpy(s).cuda()).cpu().numpy()
