@@ -331,7 +331,8 @@ def bench_batched(steps, torch):
 def bench_stream(n_frames, torch):
     """Request loop: frames (N=2048, F=4, T=32768) at Poisson arrivals, continuous
     batching (at most 8 frames a launch, two launches queued on one HIP
-    stream, slots sized from free device memory), device-resident
+    stream, slots sized from free device memory, time slices per batch size
+    tuned on the frames first), device-resident
     accumulator dumped every 256 frames into pinned buffers allocated up
     front."""
     import numpy as np
@@ -344,8 +345,12 @@ def bench_stream(n_frames, torch):
     dump_every = 256
     launcher = GpuLauncher(w.N, w.F, w.T, streams=1, graph=True, max_batch=8, queues=1,
                            dump_buffers=n_frames // dump_every + 2)
+    launcher.tune_slices(pool)
     launcher.warm(pool)
     out = {"frame": {"N": w.N, "F": w.F, "T": w.T}, "slots": launcher.slots,
+           "split_t_per_batch": {str(k): v for k, v in launcher.split_t.items()},
+           "split_ms_per_batch": {str(k): {str(s): round(t, 4) for s, t in v.items()}
+                                  for k, v in launcher.split_ms.items()},
            "max_batch": launcher.max_batch, "hip_streams": launcher.queues, "launches_in_flight": 2,
            "distinct_frames": len(pool), "cmac_per_frame": w.cmac}
 

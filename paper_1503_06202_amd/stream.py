@@ -212,7 +212,9 @@ class GpuLauncher:
     front (in turn: a dump's buffer is reused ``dump_buffers`` dumps later),
     and clears it; the next launches wait for the clear.
     ``slots`` bounds the frames admitted at once (default: what half of the
-    free device memory holds, at most 128).
+    free device memory holds, at most 128).  ``tune_slices`` times the time
+    slices per tile of every batch size on real frames and keeps the fastest
+    exact choice (the automatic count is a cost model).
     """
 
     def __init__(self, N: int, F: int, T: int, slots: Optional[int] = None, streams: int = 1,
@@ -220,7 +222,7 @@ class GpuLauncher:
                  queues: int = 1, dump_buffers: int = 4):
         import torch
 
-        from .engine import BatchPlan, vis_shape
+        from .engine import vis_shape
 
         self.torch = torch
         self.N, self.F, self.T = N, F, T
@@ -229,10 +231,13 @@ class GpuLauncher:
         self.slots = int(slots) if slots else slots_from_memory(frame_bytes, device=self.device)
         self.max_batch = max(1, min(max_batch, self.slots))
         self.graph = graph
+        self.form = form
         self.queues = max(1, int(queues))
         self.hip_streams = [torch.cuda.Stream(self.device) for _ in range(self.queues)]
-        self.plans = [{k: BatchPlan([(N, F, T)] * k, form=form, accumulate=True, shared_vis=True)
-                       for k in range(1, self.max_batch + 1)} for _ in range(self.queues)]
+        self.plans = [{k: self._plan(k, 0) for k in range(1, self.max_batch + 1)}
+                      for _ in range(self.queues)]
+        self.split_t = {k: 0 for k in range(1, self.max_batch + 1)}  # 0: the library's choice
+        self.split_ms: Dict[int, Dict[int, float]] = {}
         shape = vis_shape(N, F)
         self.acc = [torch.zeros(shape, dtype=torch.int32, device=self.device)
                     for _ in range(streams)]
@@ -272,6 +277,62 @@ class GpuLauncher:
         ev.record(s)
         self._last[q] = ev
         return ev
+
+    def _plan(self, k: int, split: int):
+        from .engine import BatchPlan
+
+        return BatchPlan([(self.N, self.F, self.T)] * k, form=self.form, accumulate=True,
+                         shared_vis=True, split_t=[split] * k)
+
+    def tune_slices(self, samples, candidates: Sequence[int] = (0, 2, 3, 4),
+                    reps: int = 5) -> Dict[int, int]:
+        """Time slices per tile for every batch size k: each candidate (0: the
+        library's automatic count) is timed as this launcher runs it (a
+        batched plan of k frames adding into one accumulator, graph-replayed
+        on the first HIP stream) on ``samples``; the fastest whose result is
+        bit-identical to the automatic count's replaces the plans of size k on
+        every HIP stream.  The launcher's accumulators are not touched."""
+        torch = self.torch
+        s = self.hip_streams[0]
+        scratch = torch.zeros_like(self.acc[0])
+        # the clocks of an idle GPU ramp up under load: run the largest batch
+        # for a while before timing anything
+        big = self.plans[0][self.max_batch]
+        frames = [samples[i % len(samples)] for i in range(self.max_batch)]
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.3:
+            big.correlate(frames, [scratch] * self.max_batch, stream=s, graph=self.graph)
+            torch.cuda.synchronize(self.device)
+        for k in range(1, self.max_batch + 1):
+            frames = [samples[i % len(samples)] for i in range(k)]
+            ref, times = None, {}
+            n = max(reps, -(-reps * 4 // k))  # at least about 4 reps' worth of frames
+            for split in dict.fromkeys([0] + [int(c) for c in candidates]):
+                plan = self._plan(k, split)
+                with torch.cuda.stream(s):
+                    scratch.zero_()
+                    plan.correlate(frames, [scratch] * k, stream=s, graph=self.graph)
+                    got = scratch.clone()
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(s)
+                    for _ in range(n):
+                        plan.correlate(frames, [scratch] * k, stream=s, graph=self.graph)
+                    e1.record(s)
+                e1.synchronize()
+                if ref is None:
+                    ref = got
+                if torch.equal(got, ref):  # never keep a count that changes a bit
+                    times[split] = e0.elapsed_time(e1) / n
+                plan.close()
+            best = min(times, key=times.get)
+            self.split_ms[k] = times
+            if best != self.split_t[k]:
+                for q in range(self.queues):
+                    self.plans[q][k].close()
+                    self.plans[q][k] = self._plan(k, best)
+                self.split_t[k] = best
+        torch.cuda.synchronize(self.device)
+        return dict(self.split_t)
 
     def warm(self, samples) -> None:
         """Run every plan once (capturing its graph) on ``samples``, then clear

@@ -10,10 +10,12 @@ from paper_1503_06202_amd.stream import Frame, GpuLauncher, RequestLoop, poisson
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("graph,queues", [(False, 1), (True, 1), (True, 2)])
-def test_request_loop_accumulates_exactly(graph, queues):
+@pytest.mark.parametrize("graph,queues,tuned", [(False, 1, False), (True, 1, False),
+                                                (True, 2, False), (True, 1, True)])
+def test_request_loop_accumulates_exactly(graph, queues, tuned):
     # one HIP stream with two launches queued (the default), or launches on
-    # two HIP streams adding into the same accumulators
+    # two HIP streams adding into the same accumulators; with slices tuned
+    # per batch size or the library's automatic count
     N, F, T, streams = 136, 2, 320, 3
     rng = np.random.default_rng(17)
     host = [rng.integers(0, 256, (T, F, N), dtype=np.uint8) for _ in range(12)]
@@ -23,6 +25,10 @@ def test_request_loop_accumulates_exactly(graph, queues):
     frames = [Frame(k, k % streams, pool[k % len(pool)], float(arr[k])) for k in range(n)]
     la = GpuLauncher(N, F, T, slots=4, streams=streams, graph=graph, max_batch=4,
                      dump_buffers=16, queues=queues)
+    if tuned:
+        choice = la.tune_slices(pool[:4], candidates=(0, 1, 2, 3))
+        assert set(choice) == {1, 2, 3, 4} and set(choice.values()) <= {0, 1, 2, 3}
+        assert all(float(la.acc[st].abs().sum()) == 0 for st in range(streams))  # untouched
     rep = RequestLoop(la, dump_every=5).run(frames)
     torch.cuda.synchronize()
     assert rep.frames == n and max(rep.batch_sizes) <= 4
