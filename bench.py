@@ -73,10 +73,10 @@ def parse():
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
     ap.add_argument("--forms",
-                    default="f8,precision,pathfinder,gated,shifted,flagged,beams,batched,stream",
-                    help="other forms reported beside the headline line (comma list of f8, "
-                         "precision, pathfinder, gated, shifted, flagged, beams, batched, stream; "
-                         "empty for none)")
+                    default="tuner,f8,precision,pathfinder,gated,shifted,flagged,beams,batched,stream",
+                    help="other forms reported beside the headline line (comma list of tuner, "
+                         "f8, precision, pathfinder, gated, shifted, flagged, beams, batched, "
+                         "stream; empty for none)")
     ap.add_argument("--stream-frames", type=int, default=1000)
     return ap.parse_args()
 
@@ -290,6 +290,18 @@ def bench_pathfinder(steps, torch):
 
 def vis_shape_of(w):
     return (w.F, w.baselines, 2)
+
+
+def bench_tuner(d, w, torch):
+    """The plain autotuner on the main frame: every tile shape and time-slice
+    count (0 = the automatic configuration the headline step uses), timed on
+    the frame, the candidates checked bit-identical to each other, and its pick."""
+    from paper_1503_06202_amd import tune
+
+    times = {}
+    kernel, split = tune.tune_plain(w.N, w.F, w.T, cache_path=None, frame=d, reps=5, times=times)
+    return {"workload": w.name, "kernel": kernel, "split_t": split,
+            "ms_per_frame": {k: round(v, 4) for k, v in times.items()}}
 
 
 def bench_batched(steps, torch):
@@ -630,6 +642,9 @@ def main():
     plan.close()
     forms = [f for f in args.forms.split(",") if f]
     extra = {}
+    if "tuner" in forms:
+        _log("bench: autotuner on the main frame")
+        extra["tuner"] = bench_tuner(d, w, torch)
     if "f8" in forms:
         _log("bench: fp8 form")
         extra["fp8"] = bench_fp8(d, w, args.steps, torch)

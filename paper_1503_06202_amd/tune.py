@@ -89,11 +89,12 @@ def _time_plain(shape, form: str, kernel: int, split: int, frame, reps: int):
 def tune_plain(N: int, F: int, T: int, form: str = "i8", kernels: Iterable[int] = PLAIN_KERNELS,
                splits: Iterable[int] = PLAIN_SPLITS, reps: int = 5,
                cache_path: Optional[str] = DEFAULT_CACHE, seed: int = 4321, frame=None,
-               log=None) -> Tuple[int, int]:
+               log=None, times: Optional[Dict[str, float]] = None) -> Tuple[int, int]:
     """(kernel, split_t) for ``Plan.set_tuning`` on frames of this shape.
 
     ``frame`` (optional): a device frame of the shape to time on, instead of a
-    freshly generated one.
+    freshly generated one.  ``times`` (optional): filled with the median
+    milliseconds of every exact candidate, keyed "kernel/split".
     """
     import torch
 
@@ -102,6 +103,8 @@ def tune_plain(N: int, F: int, T: int, form: str = "i8", kernels: Iterable[int] 
     key = "plain/" + _key(_arch(), form, N, F, T)
     cache = load_cache(cache_path) if cache_path else {}
     if key in cache:
+        if times is not None:
+            times.update(cache[key].get("ms", {}))
         return int(cache[key]["kernel"]), int(cache[key]["split_t"])
     if frame is None:
         frame = torch.from_numpy(synth.gen_frame(N, F, T, seed, "gauss",
@@ -126,6 +129,8 @@ def tune_plain(N: int, F: int, T: int, form: str = "i8", kernels: Iterable[int] 
     choice = min(results, key=results.get)
     cache[key] = {"kernel": choice[0], "split_t": choice[1],
                   "ms": {f"{k}/{s}": v for (k, s), v in sorted(results.items())}}
+    if times is not None:
+        times.update(cache[key]["ms"])
     if log:
         log(f"tune: {key}: " + ", ".join(f"kernel {k} split {s}: {v:.3f} ms"
                                           for (k, s), v in sorted(results.items())) +
