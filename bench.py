@@ -73,7 +73,8 @@ def parse():
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="measured HBM bytes per launch (from rocprofv3 counters), if present")
     ap.add_argument("--forms",
-                    default="tuner,f8,precision,pathfinder,gated,shifted,flagged,beams,batched,stream",
+                    default="tuner,f8,precision,pathfinder,gated,shifted,flagged,beams,batched,"
+                            "stream",
                     help="other forms reported beside the headline line (comma list of tuner, "
                          "f8, precision, pathfinder, gated, shifted, flagged, beams, batched, "
                          "stream; empty for none)")

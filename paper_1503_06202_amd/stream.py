@@ -20,8 +20,8 @@ previous one leaves idle as it drains; on full-size frames two concurrent
 batched kernels served fewer frames per second than two queued launches, and
 with a longer p99.  Frames of one stream may share a launch, and launches on
 any HIP stream add into the same accumulator: the batched kernels add with
-exact int32 atomics, whose order does not matter.  Latency is measured from a frame's arrival to
-the completion of the launch that carried it.
+exact int32 atomics, whose order does not matter.  Latency is measured from a
+frame's arrival to the completion of the launch that carried it.
 
 The loop talks to a launcher (``launch``, ``ready``, ``dump``); the GPU
 launcher below drives ``libxeng.so`` through batched plans, one set per HIP
@@ -206,7 +206,7 @@ class GpuLauncher:
     plan's automatic time slices are chosen for k
     frames' worth of tiles, so that a lone frame spreads over the whole GPU
     as well as a full batch does.  Every stream's accumulator lives on the
-    GPU; frames add into it (shared, atomic) from either HIP stream.  ``dump``
+    GPU; frames add into it (shared, atomic) from any HIP stream.  ``dump``
     is ordered after the last launch on every HIP stream, copies the
     accumulator into one of ``dump_buffers`` pinned host buffers allocated up
     front (in turn: a dump's buffer is reused ``dump_buffers`` dumps later),
@@ -301,6 +301,8 @@ class GpuLauncher:
         frames = [samples[i % len(samples)] for i in range(self.max_batch)]
         t0 = time.perf_counter()
         while time.perf_counter() - t0 < 0.3:
+            with torch.cuda.stream(s):
+                scratch.zero_()  # keep the sums far from the int32 range
             big.correlate(frames, [scratch] * self.max_batch, stream=s, graph=self.graph)
             torch.cuda.synchronize(self.device)
         for k in range(1, self.max_batch + 1):
@@ -313,7 +315,8 @@ class GpuLauncher:
                     scratch.zero_()
                     plan.correlate(frames, [scratch] * k, stream=s, graph=self.graph)
                     got = scratch.clone()
-                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
                     e0.record(s)
                     for _ in range(n):
                         plan.correlate(frames, [scratch] * k, stream=s, graph=self.graph)
