@@ -33,12 +33,56 @@ since_dump=...)``) with the same result as an uninterrupted run.
 from __future__ import annotations
 
 import collections
+import ctypes
 import dataclasses
 import math
+import os
 import time
 from typing import Any, Callable, Deque, Dict, List, Optional, Sequence
 
 import numpy as np
+
+
+class Markers:
+    """roctx ranges (ROCm's marker API, which ``rocprofv3 --marker-trace``
+    records beside the kernels), or no-ops where no roctx library loads.
+    The request loop opens one range per run, per launch and per dump."""
+
+    def __init__(self):
+        self._push = self._pop = None
+        lib_dir = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+        for name in ("librocprofiler-sdk-roctx.so.1", "libroctx64.so.4"):
+            for path in (os.path.join(lib_dir, name), name):
+                try:
+                    lib = ctypes.CDLL(path)
+                except OSError:
+                    continue
+                lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+                lib.roctxRangePushA.restype = ctypes.c_int
+                lib.roctxRangePop.argtypes = []
+                lib.roctxRangePop.restype = ctypes.c_int
+                self._push, self._pop = lib.roctxRangePushA, lib.roctxRangePop
+                self.library = path
+                return
+        self.library = None
+
+    def push(self, message: str) -> None:
+        if self._push is not None:
+            self._push(message.encode())
+
+    def pop(self) -> None:
+        if self._pop is not None:
+            self._pop()
+
+
+_markers: Optional[Markers] = None
+
+
+def default_markers() -> Markers:
+    global _markers
+    if _markers is None:
+        _markers = Markers()
+    return _markers
 
 
 @dataclasses.dataclass
@@ -94,7 +138,7 @@ class RequestLoop:
 
     def __init__(self, launcher, max_inflight: Optional[int] = None, dump_every: int = 256,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep, markers=None):
         if max_inflight is None:
             max_inflight = 2  # the next launch waits on the device, not on the host
         if launcher.slots < 1 or max_inflight < 1 or dump_every < 1:
@@ -105,6 +149,7 @@ class RequestLoop:
         self.dump_every = dump_every
         self.clock = clock
         self.sleep = sleep
+        self.markers = markers if markers is not None else default_markers()
 
     def run(self, frames: Sequence[Frame], since_dump: Optional[Dict[int, int]] = None) -> Report:
         """Serve ``frames``; ``since_dump`` resumes an integration (frames already
@@ -122,6 +167,8 @@ class RequestLoop:
         dumps: List[Any] = []
         batch_sizes: List[int] = []
         finished: List[Frame] = []
+        mk = self.markers
+        mk.push(f"request loop: {len(frames)} frames")
         while arriving or waiting or admitted or inflight:
             t = now()
             while arriving and arriving[0].arrival <= t:
@@ -151,7 +198,9 @@ class RequestLoop:
                 for f in batch:
                     f.launched = tl
                     f.batch = len(batch)
+                mk.push(f"launch: {len(batch)} frames")
                 token = self.launcher.launch(batch)
+                mk.pop()
                 inflight.append((token, batch))
                 batch_sizes.append(len(batch))
                 for f in batch:
@@ -161,7 +210,9 @@ class RequestLoop:
                 # count is kept)
                 for st in sorted({f.stream for f in batch}):
                     if counts[st] >= self.dump_every:
+                        mk.push(f"dump: stream {st}, {counts[st]} frames")
                         dumps.append((st, counts[st], self.launcher.dump(st)))
+                        mk.pop()
                         counts[st] = 0
                 continue
             blocked = bool(admitted) and len(inflight) >= self.max_inflight
@@ -175,6 +226,7 @@ class RequestLoop:
                     if dt > 0:
                         self.sleep(min(dt, 0.001))
         wall = now()
+        mk.pop()
         lat = np.array([f.latency * 1e3 for f in finished])
         rep = Report(len(finished), wall, lat, batch_sizes, dumps)
         rep.pending = dict(counts)  # frames integrated since the last dump, per stream

@@ -217,3 +217,41 @@ def test_loop_matches_single_server_model(max_inflight):
     want = single_server_latencies(arrivals, lambda k: fixed + per * k, max_inflight, 8)
     assert np.allclose(got, want, rtol=0, atol=1e-9)
     assert np.percentile(got, 99) > 5 * (fixed + per)  # a loaded queue, not an idle one
+
+
+class RecordingMarkers:
+    def __init__(self):
+        self.events = []
+
+    def push(self, message):
+        self.events.append(("push", message))
+
+    def pop(self):
+        self.events.append(("pop", None))
+
+
+def test_loop_opens_a_marker_range_per_run_launch_and_dump():
+    clk = VClock()
+    la = FakeLauncher(clk, slots=3, service_s=0.001)
+    mk = RecordingMarkers()
+    fr = frames_for(30, 2, rate=2000.0, seed=4)
+    rep = RequestLoop(la, max_inflight=2, dump_every=6, clock=clk, sleep=clk.sleep,
+                      markers=mk).run(fr)
+    depth, peak = 0, 0
+    for kind, _ in mk.events:  # balanced and properly nested
+        depth += 1 if kind == "push" else -1
+        assert depth >= 0
+        peak = max(peak, depth)
+    assert depth == 0 and peak == 2
+    pushes = [m for kind, m in mk.events if kind == "push"]
+    assert pushes[0] == "request loop: 30 frames"
+    assert sum(m.startswith("launch: ") for m in pushes) == len(rep.batch_sizes)
+    assert sum(m.startswith("dump: ") for m in pushes) == len(rep.dumps) > 0
+
+
+def test_default_markers_load_or_do_nothing():
+    from paper_1503_06202_amd.stream import Markers
+
+    mk = Markers()  # a roctx library where ROCm is installed, else no-ops
+    mk.push("test range")
+    mk.pop()
